@@ -1,0 +1,251 @@
+"""Seeded synthetic inputs for the twofold hot path.
+
+Both the GPU library's tests and benchmark and the oracle's tests draw their
+inputs from here.  The module holds none of the twofold method's
+arithmetic: only random draws (numpy PCG64 streams), assembly of binary64 /
+binary32 values from random bits, one plain multiply that forms each
+operand's low part, and (in ``illdot.c``) an exact-integer construction of
+ill-conditioned dot products.
+
+Every generator is a pure function of its arguments.  Streams are keyed by
+``numpy.random.SeedSequence(seed, spawn_key=(purpose, ...))`` so each array
+has its own stream and draw order inside a stream is stated per function.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfgen.so")
+SOURCE = os.path.join(_HERE, "illdot.c")
+
+# Stream keys (first element of the spawn key).
+_K_X, _K_Y, _K_AXPY, _K_HORNER, _K_DOT = 1, 2, 3, 4, 5
+
+F64 = np.dtype(np.float64)
+F32 = np.dtype(np.float32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the exact ill-conditioned-dot generator with gcc."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", tmp, SOURCE, "-lm"], check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def _gen_lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        for name in ("tfgen_illdot_f64", "tfgen_illdot_f32", "tfgen_product_split_f64",
+                     "tfgen_product_split_f32"):
+            getattr(_lib, name).restype = None
+        _lib.tfgen_exact_dot_f64.restype = C.c_double
+    return _lib
+
+
+def rng(seed: int, *key: int) -> np.random.Generator:
+    """Independent PCG64 stream for (seed, key)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=tuple(key))))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Twofold operands: sign-uniform, mantissa uniform in [1, 2), exponent
+# uniform in [exp_lo, exp_hi]; low part x1 = x0 * (u * 2^-p) with u uniform
+# in [-1, 1) and p the precision (53 or 24).
+# ---------------------------------------------------------------------------
+
+def twofold_operand(n: int, seed: int, stream: int, dtype=F64, exp_lo: int = -20,
+                    exp_hi: int = 20):
+    """(x0, x1) for one operand.
+
+    Draw order in stream (seed, stream): sign bits (n integers in {0, 1}),
+    exponents (n integers in [exp_lo, exp_hi]), mantissa fractions (n
+    integers in [0, 2^52) or [0, 2^23)), u (n doubles uniform in [-1, 1)).
+    x0 is assembled bit by bit, so its mantissa is exactly 1 + k 2^-52
+    (2^-23 for binary32).
+    """
+    dtype = np.dtype(dtype)
+    g = rng(seed, stream)
+    sign = g.integers(0, 2, n, dtype=np.uint64)
+    expo = g.integers(exp_lo, exp_hi + 1, n, dtype=np.int64)
+    if dtype == F64:
+        frac = g.integers(0, 1 << 52, n, dtype=np.uint64)
+        bits = (sign << np.uint64(63)) | ((expo + 1023).astype(np.uint64) << np.uint64(52)) | frac
+        del sign, expo, frac
+        x0 = bits.view(np.float64)
+        u = g.uniform(-1.0, 1.0, n)
+        u *= 2.0 ** -53
+        x1 = x0 * u
+    elif dtype == F32:
+        frac = g.integers(0, 1 << 23, n, dtype=np.uint64)
+        bits = ((sign << np.uint64(31)) | ((expo + 127).astype(np.uint64) << np.uint64(23)) | frac)
+        del sign, expo, frac
+        x0 = bits.astype(np.uint32).view(np.float32)
+        u = g.uniform(-1.0, 1.0, n).astype(np.float32)
+        u *= np.float32(2.0 ** -24)
+        x1 = x0 * u
+    else:
+        raise TypeError(dtype)
+    return np.ascontiguousarray(x0), x1
+
+
+def elementwise(op: str, n: int, seed: int = 0, dtype=F64):
+    """Operands of one elementwise call: dict with x0, x1, y0, y1.
+
+    x comes from stream 1 and y from stream 2.  For sqrt the argument is
+    made non-negative without changing its value's magnitude: x0 <- |x0|
+    and x1 <- sign(x0) x1, i.e. the operand becomes |x|.  Divisors need no
+    adjustment: |y0| >= 2^-20 already.
+    """
+    x0, x1 = twofold_operand(n, seed, _K_X, dtype)
+    if op == "sqrt":
+        neg = np.signbit(x0)
+        x0 = np.abs(x0)
+        x1 = np.where(neg, -x1, x1)
+        return {"x0": x0, "x1": x1}
+    y0, y1 = twofold_operand(n, seed, _K_Y, dtype)
+    return {"x0": x0, "x1": x1, "y0": y0, "y1": y1}
+
+
+AXPY_A = (0.7, 1e-17)
+
+
+def axpy_case(n: int, seed: int = 0, dtype=F64):
+    """a = (0.7, 1e-17) rounded to the working type; x, y twofold operands."""
+    dtype = np.dtype(dtype)
+    a = np.array(AXPY_A, dtype=dtype)
+    x0, x1 = twofold_operand(n, seed, _K_AXPY, dtype)
+    y0, y1 = twofold_operand(n, seed, _K_AXPY + 100, dtype)
+    return {"a": a, "x0": x0, "x1": x1, "y0": y0, "y1": y1}
+
+
+def horner_case(n: int, seed: int = 0, dtype=F64, degree: int = 8):
+    """Coefficients c[0..degree] uniform in [-1, 1] with c[1] = 0; x0 uniform
+    in [0.9, 1.1]; x1 = x0 * (u 2^-p).
+
+    Draw order in stream (seed, 4): degree+1 coefficient doubles, then n
+    doubles for x0, then n doubles for u.
+    """
+    dtype = np.dtype(dtype)
+    g = rng(seed, _K_HORNER)
+    c = g.uniform(-1.0, 1.0, degree + 1)
+    if degree >= 1:
+        c[1] = 0.0
+    x0 = g.uniform(0.9, 1.1, n)
+    u = g.uniform(-1.0, 1.0, n)
+    if dtype == F64:
+        u *= 2.0 ** -53
+        x1 = x0 * u
+        return {"c": c, "x0": x0, "x1": x1}
+    c32 = c.astype(np.float32)
+    x032 = x0.astype(np.float32)
+    u32 = u.astype(np.float32) * np.float32(2.0 ** -24)
+    return {"c": c32, "x0": x032, "x1": x032 * u32}
+
+
+# ---------------------------------------------------------------------------
+# Ill-conditioned dot products (exact construction in illdot.c)
+# ---------------------------------------------------------------------------
+
+def _illdot_once(n, cond, e_max, seed, dtype):
+    g = rng(seed, _K_DOT, int(round(math.log10(cond) * 100)), e_max)
+    h = n // 2
+    u = g.uniform(-1.0, 1.0, n)
+    v = g.uniform(-1.0, 1.0, n)
+    e1 = g.integers(0, e_max + 1, h, dtype=np.int64).astype(np.int32)
+    if h >= 1:
+        e1[0] = e_max
+        e1[h - 1] = 0
+    e1 = np.ascontiguousarray(e1)
+    stats = np.zeros(3, np.float64)
+    lib = _gen_lib()
+    if dtype == F64:
+        x, y = np.empty(n, np.float64), np.empty(n, np.float64)
+        lib.tfgen_illdot_f64(C.c_int64(n), C.c_int(e_max), C.c_double(cond), _ptr(u), _ptr(v),
+                             _ptr(e1), _ptr(x), _ptr(y), _ptr(stats))
+    else:
+        u32 = np.ascontiguousarray(u.astype(np.float32))
+        v32 = np.ascontiguousarray(v.astype(np.float32))
+        x, y = np.empty(n, np.float32), np.empty(n, np.float32)
+        lib.tfgen_illdot_f32(C.c_int64(n), C.c_int(e_max), C.c_double(cond), _ptr(u32),
+                             _ptr(v32), _ptr(e1), _ptr(x), _ptr(y), _ptr(stats))
+    return x, y, {"cond": float(stats[0]), "dot": float(stats[1]), "e_max": e_max}
+
+
+def illdot_case(n: int, cond: float, seed: int = 0, dtype=F64, max_tries: int = 8):
+    """Dot instance (x, y) of length n (even) with condition number
+    2 sum|x_i y_i| / |x^T y| close to ``cond``.
+
+    First-half exponents are drawn uniformly in [0, e_max], starting from
+    e_max = floor(log2(cond) / 2).  When the achieved condition number is
+    more than a factor 4 away from the target, e_max moves by
+    round(log2(ratio) / 2) and the instance is drawn again (the draws are
+    keyed by e_max, so the result is a pure function of the arguments).
+    Returns dict x, y, cond (achieved), dot (exact x^T y rounded once),
+    e_max.
+    """
+    dtype = np.dtype(dtype)
+    if n % 2:
+        raise ValueError("illdot_case needs an even n")
+    e_max = max(0, int(math.floor(math.log2(cond) / 2.0)))
+    best = None
+    for _ in range(max_tries):
+        x, y, st = _illdot_once(n, cond, e_max, seed, dtype)
+        ratio = st["cond"] / cond
+        if best is None or abs(math.log(ratio)) < abs(math.log(best[2]["cond"] / cond)):
+            best = (x, y, st)
+        if 0.25 <= ratio <= 4.0:
+            break
+        step = int(round(math.log2(ratio) / 2.0)) or (1 if ratio > 1 else -1)
+        new = max(0, e_max - step)
+        if new == e_max:
+            break
+        e_max = new
+    x, y, st = best
+    return {"x": x, "y": y, "cond": st["cond"], "dot": st["dot"], "e_max": st["e_max"]}
+
+
+def product_split(x, y):
+    """(hi, lo) with hi = fl(x_i y_i) and lo = x_i y_i - hi exactly, from the
+    exact integer product: twofold leaves whose sum is exactly x^T y."""
+    dt = np.asarray(x).dtype
+    x = np.ascontiguousarray(x)
+    y = np.ascontiguousarray(y)
+    hi, lo = np.empty_like(x), np.empty_like(x)
+    fn = _gen_lib().tfgen_product_split_f64 if dt == F64 else _gen_lib().tfgen_product_split_f32
+    fn(C.c_int64(x.size), _ptr(x), _ptr(y), _ptr(hi), _ptr(lo))
+    return hi, lo
+
+
+def sum_case(n: int, cond: float, seed: int = 0, dtype=F64):
+    """Twofold sum instance: the exact product split of an ill-conditioned
+    dot instance, so sum(x0_i + x1_i) = x^T y exactly."""
+    d = illdot_case(n, cond, seed, dtype)
+    x0, x1 = product_split(d["x"], d["y"])
+    return {"x0": x0, "x1": x1, "cond": d["cond"], "dot": d["dot"], "e_max": d["e_max"]}
+
+
+def exact_dot_f64(x, y) -> float:
+    """Exact x^T y of binary64 vectors, rounded once (for reports)."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    return float(_gen_lib().tfgen_exact_dot_f64(C.c_int64(x.size), _ptr(x), _ptr(y)))
