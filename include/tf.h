@@ -1,0 +1,201 @@
+/*
+ * tf.h - twofold fast arithmetic on AMD Instinct MI355X (gfx950).
+ *
+ * A twofold is an unevaluated sum z0 + z1 of two floating-point numbers of
+ * one working type (E. Latkin, "Twofold fast arithmetic", 2014): z0 is
+ * bitwise the standard IEEE result of the operation on the main parts, and
+ * z1 approximates its deviation dz0 = z - z0 from the exact result z.  The
+ * library evaluates the paper's algorithms elementwise over large arrays
+ * and in a few streaming kernels built from them.
+ *
+ * Data layout: structure of arrays.  A twofold array of n elements is two
+ * separate arrays of n values, its main parts (z0) and its error parts (z1).
+ * A NULL error-part pointer on an input marks a "dotted" operand (a plain
+ * number), which selects the paper's cheaper *.1 / *.1.1 variants.  Outputs
+ * always have both parts.
+ *
+ * Conventions for every call below:
+ *   dtype      TF_F64 (binary64, double) or TF_F32 (binary32, float); all
+ *              arrays of one call hold that type.
+ *   n          number of elements, n >= 0; n == 0 launches nothing
+ *              (reductions then write (+0, +0)).
+ *   pointers   device pointers (HBM), owned by the caller, unless marked
+ *              HOST.  Elementwise calls never allocate.  An output may alias
+ *              an input exactly (in place); partial overlap is undefined.
+ *              Any natural alignment works; 16-byte alignment of every
+ *              array selects the 128-bit vector path.
+ *   stream     HIP stream the kernels are enqueued on (0 = null stream).
+ *              Calls return once the work is enqueued; results are
+ *              visible in stream order.  The library never synchronises.
+ *   return     TF_OK, or a negative TF_E* code for misuse (NULL required
+ *              pointer, n < 0, unknown dtype, degree out of range, workspace
+ *              too small) or a failed launch.  NaN, infinities, division by
+ *              zero and square roots of negatives are data, not errors: they
+ *              propagate through the basic operations exactly as the paper
+ *              prescribes (no special-case handling).
+ *
+ * Every kernel is built without fast-math, with floating-point contraction
+ * off, IEEE division and square root, and denormals kept, so each step is
+ * one correctly rounded IEEE operation (round to nearest, ties to even).
+ */
+#ifndef TF_H
+#define TF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Working types. */
+#define TF_F32 1
+#define TF_F64 2
+
+/* Status codes. */
+#define TF_OK 0
+#define TF_EINVAL (-1)  /* invalid argument */
+#define TF_EDEVICE (-2) /* a HIP call or kernel launch failed */
+#define TF_ENOMEM (-3)  /* workspace too small / allocation failed */
+#define TF_EBUSY (-4)   /* resource temporarily exhausted (serving) */
+#define TF_ESTATE (-5)  /* call not valid in the object's current state */
+
+/* Human-readable text of a status code (static storage). */
+const char *tf_strerror(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int tf_version(void);
+
+/* ------------------------------------------------------------------------
+ * Elementwise twofold operations (Algorithms section of the paper).
+ * z_i = x_i op y_i for i < n, each operand twofold (x0, x1) or dotted
+ * (x1 == NULL).  z0 and z1 are required outputs of n elements.
+ * ---------------------------------------------------------------------- */
+
+/* Add: ATF1 for two twofolds, z0 = x0 + y0, z1 = (x1 + y1) + err(x0 + y0);
+ * ATF1.1 when one operand is dotted (z1 = RN(dz0) exactly); the exact
+ * Two-Sum (Algorithm 1.2) when both are dotted. */
+int tf_add(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+           const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Subtract: STF1, z0 = x0 - y0, z1 = (x1 - y1) + err(x0 - y0); STF1.1 when y
+ * is dotted; err(x0 - y0) - y1 when x is dotted; the exact Two-Diff
+ * (Algorithm 2.2, with a - b = d + t) when both are dotted. */
+int tf_sub(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+           const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Multiply: MTF1, z0 = x0 y0, z1 = (e00 + x1 y1) + (x0 y1 + x1 y0) with e00
+ * the fma error of x0 y0; MTF1.1 when one operand is dotted; the exact
+ * Two-Product (Algorithm 3) when both are dotted. */
+int tf_mul(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+           const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Divide: DTF1, z0 = x0 / y0, r0 = fma(-z0, y0, x0), r1 = fma(-z0, y1, x1),
+ * z1 = (r0 + r1) / (y0 + y1); DTF1.1 when y is dotted; DTF1.1.1 when both
+ * are dotted (z1 = RN(dz0)); DTF1 with x1 = +0 when only x is dotted.
+ * y0 == 0 gives infinite or NaN parts, as the IEEE operations do. */
+int tf_div(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+           const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Square root: RTF1 for a twofold argument (z0 = sqrt(x0); renormalise x with
+ * Two-Sum; one Newton step RPF1 on the renormalised pair; subtract z0 with
+ * STF1.1 and add the two parts); RPF1.1 for a dotted argument,
+ * z1 = fma(-z0, z0, x0) / (2 z0).  sqrt(0) gives z1 = NaN (0/0) and a
+ * negative argument NaN parts, by the formulas themselves. */
+int tf_sqrt(int dtype, int64_t n, const void *x0, const void *x1, void *z0, void *z1,
+            hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Streaming kernels composed of the operations above.
+ * ---------------------------------------------------------------------- */
+
+/* axpy: z_i = a x_i + y_i with a twofold scalar a = (a[0], a[1]) (HOST
+ * pointer to 2 values of dtype).  t = MTF1(a, x_i) (MTF1.1 if x is dotted),
+ * z_i = ATF1(t, y_i) (ATF1.1 if y is dotted). */
+int tf_axpy(int dtype, int64_t n, const void *a, const void *x0, const void *x1,
+            const void *y0, const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Horner evaluation of p(x_i) = c[0] + c[1] x_i + ... + c[d] x_i^d with
+ * dotted coefficients c (HOST pointer to degree + 1 values of dtype),
+ * 0 <= degree <= TF_MAX_DEGREE: r = (c[d], +0); for k = d-1 .. 0,
+ * r = ATF1.1(MTF1(r, x_i), c[k]) (MTF1.1 if x is dotted). */
+#define TF_MAX_DEGREE 32
+int tf_horner(int dtype, int64_t n, int degree, const void *c, const void *x0,
+              const void *x1, void *z0, void *z1, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Reductions with a twofold accumulator over a fixed pairwise tree.
+ *
+ * Tree: the leaves (index order) are cut into tiles of 256 consecutive
+ * indices, a short last tile padded with zero leaves; within a tile the
+ * tree is complete with adjacent pairing (level 1 joins leaves 2i, 2i+1,
+ * and so on for 8 levels); the tile results are joined by the same adjacent
+ * pairing, their count padded with (+0, +0) to a power of two.  Every node
+ * is ATF1(left, right); dotted leaves of tf_sum enter through Two-Sum at
+ * level 1.  The tree depends only on n, never on the launch geometry, so
+ * results are bitwise reproducible.
+ *
+ * out: DEVICE pointer to 2 values of dtype, written (z0, z1).
+ * work / work_bytes: caller-owned device workspace of at least
+ * tf_reduce_workspace_bytes(dtype, n) bytes (may be NULL when that is 0).
+ * ---------------------------------------------------------------------- */
+size_t tf_reduce_workspace_bytes(int dtype, int64_t n);
+
+/* Sum of the twofold leaves (x0_i, x1_i), or of the dotted x0_i when x1 is
+ * NULL. */
+int tf_sum(int dtype, int64_t n, const void *x0, const void *x1, void *out, void *work,
+           size_t work_bytes, hipStream_t stream);
+
+/* Dot product: leaves are the twofold products of x_i and y_i, Two-Product
+ * for dotted x and y (the paper's twofold accumulator of plain numbers),
+ * MTF1 for twofold x and y, MTF1.1 for one twofold and one dotted. */
+int tf_dot(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+           const void *y1, void *out, void *work, size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Plain (non-twofold) counterparts: the same kernels' standard results only
+ * (z = the z0 the twofold call would produce, bit for bit), for measuring
+ * the twofold/plain slowdown.  Arguments as above with single arrays.
+ * ---------------------------------------------------------------------- */
+int tf_plain_add(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
+int tf_plain_sub(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
+int tf_plain_mul(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
+int tf_plain_div(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
+int tf_plain_sqrt(int dtype, int64_t n, const void *x, void *z, hipStream_t stream);
+/* z_i = a[0] x_i + y_i (a: HOST pointer to one value of dtype). */
+int tf_plain_axpy(int dtype, int64_t n, const void *a, const void *x, const void *y, void *z,
+                  hipStream_t stream);
+/* r = c[d]; r = r x_i + c[k] for k = d-1 .. 0 (multiply, then add). */
+int tf_plain_horner(int dtype, int64_t n, int degree, const void *c, const void *x, void *z,
+                    hipStream_t stream);
+/* Plain sums over the same tree (out: one value). */
+int tf_plain_sum(int dtype, int64_t n, const void *x, void *out, void *work, size_t work_bytes,
+                 hipStream_t stream);
+int tf_plain_dot(int dtype, int64_t n, const void *x, const void *y, void *out, void *work,
+                 size_t work_bytes, hipStream_t stream);
+
+/* Memory roofline probe (the paper's vmem test): reads x and y, writes z = x,
+ * n elements of dtype; moves the bytes of a plain binary operation with no
+ * arithmetic. */
+int tf_vmem(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Launch tuning (process-wide).  Results never depend on these settings.
+ *   TF_CFG_EW_BLOCKS_PER_CU    cap on the elementwise grid, in blocks per
+ *                              compute unit (0 = one block per 256 threads'
+ *                              worth of work, no cap; default 0)
+ *   TF_CFG_RED_TILES_PER_BLOCK 256-leaf tiles per reduction block, a power
+ *                              of two in [1, 64] (default 64)
+ * Returns the previous value, or TF_EINVAL for an unknown key or value.
+ * ---------------------------------------------------------------------- */
+#define TF_CFG_EW_BLOCKS_PER_CU 1
+#define TF_CFG_RED_TILES_PER_BLOCK 2
+int64_t tf_config(int key, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TF_H */

@@ -1,0 +1,242 @@
+// C-ABI entry points: argument checks, variant and type dispatch, launch.
+#include <stdint.h>
+
+#include "tf_internal.hpp"
+
+namespace tf {
+
+Config &config() {
+    static Config c;
+    return c;
+}
+
+int num_cus() {
+    static int cus = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            return 256;
+        return v;
+    }();
+    return cus;
+}
+
+static bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
+
+static Launch make_launch(hipStream_t stream, std::initializer_list<const void *> ptrs) {
+    Launch L;
+    L.stream = stream;
+    L.aligned = true;
+    for (const void *p : ptrs) L.aligned = L.aligned && aligned16(p);
+    const int64_t bpc = config().ew_blocks_per_cu;
+    L.cap = bpc > 0 ? bpc * num_cus() : 0;
+    return L;
+}
+
+static int size_of(int dtype) { return dtype == TF_F64 ? 8 : dtype == TF_F32 ? 4 : 0; }
+
+static int finish() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TF_OK : TF_EDEVICE;
+}
+
+}  // namespace tf
+
+using namespace tf;
+
+#define TF_CHECK(cond)                                                                             \
+    do {                                                                                           \
+        if (!(cond)) return TF_EINVAL;                                                             \
+    } while (0)
+
+extern "C" {
+
+const char *tf_strerror(int status) {
+    switch (status) {
+    case TF_OK: return "success";
+    case TF_EINVAL: return "invalid argument";
+    case TF_EDEVICE: return "HIP call or kernel launch failed";
+    case TF_ENOMEM: return "workspace too small or out of memory";
+    case TF_EBUSY: return "resource temporarily exhausted";
+    case TF_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+int tf_version(void) { return 10000; }
+
+int64_t tf_config(int key, int64_t value) {
+    Config &c = config();
+    if (key == TF_CFG_EW_BLOCKS_PER_CU) {
+        if (value < 0) return TF_EINVAL;
+        const int64_t old = c.ew_blocks_per_cu;
+        c.ew_blocks_per_cu = value;
+        return old;
+    }
+    if (key == TF_CFG_RED_TILES_PER_BLOCK) {
+        if (value < 1 || value > 64 || (value & (value - 1))) return TF_EINVAL;
+        const int64_t old = c.red_tiles_per_block;
+        c.red_tiles_per_block = value;
+        return old;
+    }
+    return TF_EINVAL;
+}
+
+static int binary(int op, int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+                  const void *y1, void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && y0 && z0 && z1);
+    const Launch L = make_launch(stream, {x0, x1, y0, y1, z0, z1});
+    if (dtype == TF_F64) run_elementwise<double>(L, op, n, x0, x1, y0, y1, z0, z1);
+    else run_elementwise<float>(L, op, n, x0, x1, y0, y1, z0, z1);
+    return finish();
+}
+
+int tf_add(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           void *z0, void *z1, hipStream_t stream) {
+    return binary(OP_ADD, dtype, n, x0, x1, y0, y1, z0, z1, stream);
+}
+int tf_sub(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           void *z0, void *z1, hipStream_t stream) {
+    return binary(OP_SUB, dtype, n, x0, x1, y0, y1, z0, z1, stream);
+}
+int tf_mul(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           void *z0, void *z1, hipStream_t stream) {
+    return binary(OP_MUL, dtype, n, x0, x1, y0, y1, z0, z1, stream);
+}
+int tf_div(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           void *z0, void *z1, hipStream_t stream) {
+    return binary(OP_DIV, dtype, n, x0, x1, y0, y1, z0, z1, stream);
+}
+
+int tf_sqrt(int dtype, int64_t n, const void *x0, const void *x1, void *z0, void *z1,
+            hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && z0 && z1);
+    const Launch L = make_launch(stream, {x0, x1, z0, z1});
+    if (dtype == TF_F64) run_elementwise<double>(L, OP_SQRT, n, x0, x1, nullptr, nullptr, z0, z1);
+    else run_elementwise<float>(L, OP_SQRT, n, x0, x1, nullptr, nullptr, z0, z1);
+    return finish();
+}
+
+int tf_axpy(int dtype, int64_t n, const void *a, const void *x0, const void *x1, const void *y0,
+            const void *y1, void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && a);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && y0 && z0 && z1);
+    const Launch L = make_launch(stream, {x0, x1, y0, y1, z0, z1});
+    if (dtype == TF_F64) run_axpy<double>(L, n, a, x0, x1, y0, y1, z0, z1);
+    else run_axpy<float>(L, n, a, x0, x1, y0, y1, z0, z1);
+    return finish();
+}
+
+int tf_horner(int dtype, int64_t n, int degree, const void *c, const void *x0, const void *x1,
+              void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && c && degree >= 0 && degree <= TF_MAX_DEGREE);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && z0 && z1);
+    const Launch L = make_launch(stream, {x0, x1, z0, z1});
+    if (dtype == TF_F64) run_horner<double>(L, n, degree, c, x0, x1, z0, z1);
+    else run_horner<float>(L, n, degree, c, x0, x1, z0, z1);
+    return finish();
+}
+
+size_t tf_reduce_workspace_bytes(int dtype, int64_t n) {
+    const int s = size_of(dtype);
+    if (!s || n <= 0) return 0;
+    const int64_t tiles = (n + 255) / 256;
+    // one partial per tile at most (one tile per block), plus the next level
+    return (size_t)(tiles + tiles / 256 + 4) * 2 * (size_t)s;
+}
+
+static int reduce(int leaf, int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+                  const void *y1, void *out, void *work, size_t work_bytes, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && out);
+    const size_t need = tf_reduce_workspace_bytes(dtype, n);
+    if (n > 0) TF_CHECK(x0);
+    if (need > 0 && (work == nullptr || work_bytes < need)) return TF_ENOMEM;
+    const Launch L = make_launch(stream, {x0, x1, y0, y1});
+    if (dtype == TF_F64) run_reduce<double>(L, leaf, n, x0, x1, y0, y1, out, work);
+    else run_reduce<float>(L, leaf, n, x0, x1, y0, y1, out, work);
+    return finish();
+}
+
+int tf_sum(int dtype, int64_t n, const void *x0, const void *x1, void *out, void *work,
+           size_t work_bytes, hipStream_t stream) {
+    return reduce(x1 ? LEAF_SUM_T : LEAF_SUM_D, dtype, n, x0, x1, nullptr, nullptr, out, work,
+                  work_bytes, stream);
+}
+
+int tf_dot(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           void *out, void *work, size_t work_bytes, hipStream_t stream) {
+    if (n > 0) TF_CHECK(y0);
+    const int leaf = x1 && y1 ? LEAF_DOT_TT : x1 ? LEAF_DOT_TD : y1 ? LEAF_DOT_DT : LEAF_DOT_DD;
+    return reduce(leaf, dtype, n, x0, x1, y0, y1, out, work, work_bytes, stream);
+}
+
+static int plain_binary(int op, int dtype, int64_t n, const void *x, const void *y, void *z,
+                        hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x && z && (y || op == OP_SQRT));
+    const Launch L = make_launch(stream, {x, y, z});
+    if (dtype == TF_F64) run_plain<double>(L, op, n, x, y, z);
+    else run_plain<float>(L, op, n, x, y, z);
+    return finish();
+}
+
+int tf_plain_add(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream) {
+    return plain_binary(OP_ADD, dtype, n, x, y, z, stream);
+}
+int tf_plain_sub(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream) {
+    return plain_binary(OP_SUB, dtype, n, x, y, z, stream);
+}
+int tf_plain_mul(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream) {
+    return plain_binary(OP_MUL, dtype, n, x, y, z, stream);
+}
+int tf_plain_div(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream) {
+    return plain_binary(OP_DIV, dtype, n, x, y, z, stream);
+}
+int tf_plain_sqrt(int dtype, int64_t n, const void *x, void *z, hipStream_t stream) {
+    return plain_binary(OP_SQRT, dtype, n, x, nullptr, z, stream);
+}
+int tf_vmem(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream) {
+    return plain_binary(-1, dtype, n, x, y, z, stream);
+}
+
+int tf_plain_axpy(int dtype, int64_t n, const void *a, const void *x, const void *y, void *z,
+                  hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && a);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x && y && z);
+    const Launch L = make_launch(stream, {x, y, z});
+    if (dtype == TF_F64) run_plain_axpy<double>(L, n, a, x, y, z);
+    else run_plain_axpy<float>(L, n, a, x, y, z);
+    return finish();
+}
+
+int tf_plain_horner(int dtype, int64_t n, int degree, const void *c, const void *x, void *z,
+                    hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && c && degree >= 0 && degree <= TF_MAX_DEGREE);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x && z);
+    const Launch L = make_launch(stream, {x, z});
+    if (dtype == TF_F64) run_plain_horner<double>(L, n, degree, c, x, z);
+    else run_plain_horner<float>(L, n, degree, c, x, z);
+    return finish();
+}
+
+int tf_plain_sum(int dtype, int64_t n, const void *x, void *out, void *work, size_t work_bytes,
+                 hipStream_t stream) {
+    return reduce(LEAF_PSUM, dtype, n, x, nullptr, nullptr, nullptr, out, work, work_bytes, stream);
+}
+
+int tf_plain_dot(int dtype, int64_t n, const void *x, const void *y, void *out, void *work,
+                 size_t work_bytes, hipStream_t stream) {
+    if (n > 0) TF_CHECK(y);
+    return reduce(LEAF_PDOT, dtype, n, x, nullptr, y, nullptr, out, work, work_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every function include/*.h declares
+(no GPU needed: nothing is called)."""
+import ctypes
+import glob
+import os
+import re
+
+import paper_1401_6235_amd as tf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(tf\w*)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for required in ("tf_add", "tf_sub", "tf_mul", "tf_div", "tf_sqrt", "tf_axpy", "tf_horner",
+                     "tf_sum", "tf_dot"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tf.lib()
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls():
+    """Calls that touch no device: status strings, version, workspace sizes,
+    argument validation that fails before any launch."""
+    lib = tf.lib()
+    assert lib.tf_strerror(0) == b"success"
+    assert lib.tf_version() >= 10000
+    assert tf.tf_reduce_workspace_bytes(tf.TF_F64, 0) == 0
+    assert tf.tf_reduce_workspace_bytes(tf.TF_F64, 1 << 26) >= (1 << 18) * 16
+    # invalid dtype / negative n are rejected before any launch
+    assert lib.tf_add(7, ctypes.c_int64(10), None, None, None, None, None, None, None) == -1
+    assert lib.tf_add(tf.TF_F64, ctypes.c_int64(-1), None, None, None, None, None, None, None) == -1
+    assert lib.tf_horner(tf.TF_F64, ctypes.c_int64(10), 99, None, None, None, None, None, None) == -1
+    # n == 0 is a no-op that needs no pointers
+    assert lib.tf_mul(tf.TF_F32, ctypes.c_int64(0), None, None, None, None, None, None, None) == 0
+    # tuning knobs validate their values
+    assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(3)) == -1
+    assert lib.tf_config(99, ctypes.c_int64(1)) == -1

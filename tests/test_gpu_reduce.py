@@ -1,0 +1,146 @@
+"""GPU parity: twofold sum and dot, bit for bit against the oracle's tree.
+
+Covers every leaf kind (dotted and twofold sums; dotted, twofold and mixed
+dots; plain sum and dot), sizes from 0 to the full n = 2^26 instances of
+the ill-conditioned dot generator (condition numbers 1e4 .. 1e32 in
+binary64, 1e4 .. 1e16 in binary32), ragged tails, misaligned views, and
+every reduction block geometry (the tree must not depend on it).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1401_6235_amd as tf
+from gpu_util import assert_bits, step, to_gpu, to_np, torch_cuda
+from paper_1401_6235_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [np.float64, np.float32]
+SIZES = [0, 1, 2, 3, 4, 5, 255, 256, 257, 1000, 4096, 4099, 65536, 65537, 300001, 1 << 20, 5000011]
+
+
+def gpu_all(x0, x1, y0, y1):
+    g = [to_gpu(v) for v in (x0, x1, y0, y1)]
+    out = {
+        "sum_t": to_np(tf.tf_sum(g[0], g[1])),
+        "sum_d": to_np(tf.tf_sum(g[0])),
+        "dot_dd": to_np(tf.tf_dot(g[0], None, g[2], None)),
+        "dot_tt": to_np(tf.tf_dot(g[0], g[1], g[2], g[3])),
+        "dot_td": to_np(tf.tf_dot(g[0], g[1], g[2], None)),
+        "dot_dt": to_np(tf.tf_dot(g[0], None, g[2], g[3])),
+        "psum": to_np(tf.tf_plain_sum(g[0])),
+        "pdot": to_np(tf.tf_plain_dot(g[0], g[2])),
+    }
+    return out
+
+
+def oracle_all(x0, x1, y0, y1):
+    return {
+        "sum_t": np.array(oracle.sum(x0, x1)),
+        "sum_d": np.array(oracle.sum(x0)),
+        "dot_dd": np.array(oracle.dot(x0, None, y0, None)),
+        "dot_tt": np.array(oracle.dot(x0, x1, y0, y1)),
+        "dot_td": np.array(oracle.dot(x0, x1, y0, None)),
+        "dot_dt": np.array(oracle.dot(x0, None, y0, y1)),
+        "psum": np.array([oracle.plain_sum(x0)]),
+        "pdot": np.array([oracle.plain_dot(x0, y0)]),
+    }
+
+
+def random_case(n, dtype, seed):
+    g = np.random.default_rng(seed)
+    x0 = (g.standard_normal(n) * np.exp2(g.integers(-30, 30, n))).astype(dtype)
+    y0 = (g.standard_normal(n) * np.exp2(g.integers(-30, 30, n))).astype(dtype)
+    x1 = (x0.astype(np.float64) * g.uniform(-1, 1, n) * 2.0 ** -20).astype(dtype)
+    y1 = (y0.astype(np.float64) * g.uniform(-1, 1, n) * 2.0 ** -20).astype(dtype)
+    return x0, x1, y0, y1
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SIZES)
+def test_all_leaf_kinds(n, dtype):
+    step("reduce n=%d %s" % (n, np.dtype(dtype)))
+    case = random_case(n, dtype, n + 1)
+    got, want = gpu_all(*case), oracle_all(*case)
+    for k in want:
+        assert_bits(got[k], want[k], "%s n=%d" % (k, n))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_every_block_geometry_gives_the_same_bits(dtype):
+    n = 3 * (1 << 18) + 77
+    case = random_case(n, dtype, 99)
+    want = oracle_all(*case)
+    for tpb in (1, 2, 4, 8, 16, 32, 64):
+        step("geometry tiles/block=%d %s" % (tpb, np.dtype(dtype)))
+        old = tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, tpb)
+        try:
+            got = gpu_all(*case)
+        finally:
+            tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, old)
+        for k in want:
+            assert_bits(got[k], want[k], "%s tpb=%d" % (k, tpb))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_misaligned_and_special(dtype):
+    torch = torch_cuda()
+    n = 70001
+    x0, x1, y0, y1 = random_case(n + 1, dtype, 5)
+    x0[17] = np.inf
+    y0[5000] = -0.0
+    x1[9] = np.nan
+    g = [to_gpu(v)[1:] for v in (x0, x1, y0, y1)]
+    step("misaligned reduce %s" % np.dtype(dtype))
+    got = to_np(tf.tf_dot(g[0], g[1], g[2], g[3]))
+    assert_bits(got, np.array(oracle.dot(x0[1:], x1[1:], y0[1:], y1[1:])), "dot")
+    got = to_np(tf.tf_sum(g[0], None))
+    assert_bits(got, np.array(oracle.sum(x0[1:])), "sum")
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("cond", [1e4, 1e8, 1e16, 1e32])
+def test_full_size_ill_conditioned_f64(cond):
+    """n = 2^26 binary64: dot of the generator's (x, y) and sum of the exact
+    product split, checked whole against the oracle."""
+    n = 1 << 26
+    step("illdot f64 n=2^26 cond=%g (generate)" % cond)
+    d = W.illdot_case(n, cond, seed=0, dtype=np.float64)
+    hi, lo = W.product_split(d["x"], d["y"])
+    step("illdot f64 n=2^26 cond=%g (run)" % cond)
+    gx, gy, ghi, glo = (to_gpu(v) for v in (d["x"], d["y"], hi, lo))
+    assert_bits(to_np(tf.tf_dot(gx, None, gy, None)), np.array(oracle.dot(d["x"], None, d["y"], None)), "dot")
+    assert_bits(to_np(tf.tf_sum(ghi, glo)), np.array(oracle.sum(hi, lo)), "sum")
+    assert_bits(to_np(tf.tf_plain_dot(gx, gy)), np.array([oracle.plain_dot(d["x"], d["y"])]), "plain dot")
+
+
+@pytest.mark.parametrize("cond", [1e4, 1e8, 1e16])
+def test_full_size_ill_conditioned_f32(cond):
+    n = 1 << 26
+    step("illdot f32 n=2^26 cond=%g" % cond)
+    d = W.illdot_case(n, cond, seed=0, dtype=np.float32)
+    hi, lo = W.product_split(d["x"], d["y"])
+    gx, gy, ghi, glo = (to_gpu(v) for v in (d["x"], d["y"], hi, lo))
+    got = to_np(tf.tf_dot(gx, None, gy, None))
+    assert_bits(got, np.array(oracle.dot(d["x"], None, d["y"], None)), "dot")
+    assert_bits(to_np(tf.tf_sum(ghi, glo)), np.array(oracle.sum(hi, lo)), "sum")
+    # binary32 z1 against the binary64 reference deviation of z0
+    dz = oracle.ref64("dot", d["x"], None, d["y"], None, got[0])
+    assert np.isfinite(dz[0])
+
+
+def test_repeat_is_bitwise_stable():
+    case = random_case(1 << 22, np.float64, 3)
+    step("repeat determinism")
+    a = gpu_all(*case)
+    b = gpu_all(*case)
+    for k in a:
+        assert_bits(a[k], b[k], k)
+
+
+def test_workspace_too_small_is_an_error():
+    torch = torch_cuda()
+    x = torch.ones(100000, dtype=torch.float64, device="cuda")
+    with pytest.raises(tf.TwofoldError):
+        tf.tf_sum(x, None, work=torch.empty(8, dtype=torch.uint8, device="cuda"))
