@@ -194,6 +194,104 @@ int tf_vmem(int dtype, int64_t n, const void *x, const void *y, void *z, hipStre
 #define TF_CFG_RED_TILES_PER_BLOCK 2
 int64_t tf_config(int key, int64_t value);
 
+/* ------------------------------------------------------------------------
+ * Serving: verification jobs admitted continuously into one persistent
+ * kernel.
+ *
+ * A job is one sum, dot, axpy or Horner evaluation (the streaming kernels
+ * above) of its own length and type.  Jobs queue in arrival order and are
+ * admitted while a slot (at most TFS_MAX_SLOTS in flight) and room in the
+ * server's HBM pool (budget_bytes: the job's generated inputs, outputs and
+ * partials) are free; the head of the queue waits otherwise.  An admitted
+ * job's inputs are materialised on the device, its descriptor is published
+ * to the device job table, and the persistent kernel's workers claim its
+ * 16384-element units alongside those of every other job in flight, oldest
+ * job first.  Reductions use the same fixed tree as tf_sum / tf_dot and
+ * elementwise results are per element, so a job's result is bit for bit the
+ * same alone or in any mix.
+ *
+ * Per job the server reports the result (sum / dot: z0, z1; axpy / Horner:
+ * max |z0_i|, max |z1_i|, the number of elements with |z1_i| > thr |z0_i|,
+ * and order-independent digests of z0 and z1) and a flag raised when the
+ * twofold error estimate is large: |z1| > thr |z0| for sum / dot, max |z1_i|
+ * > thr max |z0_i| for axpy / Horner, or any non-finite value; thr defaults
+ * to 2^-20 (the paper's "daemon" that signals when z1 grows large against
+ * z0, Motivation and Applications sections).
+ * ---------------------------------------------------------------------- */
+#define TFS_MAX_SLOTS 64
+#define TFS_OP_SUM 0
+#define TFS_OP_DOT 1
+#define TFS_OP_AXPY 2
+#define TFS_OP_HORNER 3
+/* Job inputs: RANDOM and ILLCOND are generated on the device from the job
+ * seed with a counter-based SplitMix64 stream (ILLCOND: axpy with
+ * y ~ -a x, Horner of (x - 1)^8 near x = 1, both cancelling); PROVIDED
+ * reads caller-owned device buffers x0, x1, y0, y1 (x1 / y1 NULL = dotted),
+ * which must stay valid until the job completes. */
+#define TFS_KIND_RANDOM 0
+#define TFS_KIND_ILLCOND 1
+#define TFS_KIND_PROVIDED 2
+
+typedef struct {
+    int op;        /* TFS_OP_* */
+    int dtype;     /* TF_F32 / TF_F64 */
+    int kind;      /* TFS_KIND_* */
+    int degree;    /* Horner degree, 0 .. TF_MAX_DEGREE */
+    int64_t n;     /* 1 .. 16384 * 4095 elements */
+    uint64_t seed; /* input generator seed (RANDOM, ILLCOND) */
+    double a[2];   /* axpy twofold scalar (rounded to dtype) */
+    double c[TF_MAX_DEGREE + 1]; /* Horner coefficients (rounded to dtype) */
+    double threshold;            /* flag threshold; 0 selects 2^-20 */
+    const void *x0, *x1, *y0, *y1; /* PROVIDED inputs (device pointers) */
+} tfs_job;
+
+typedef struct {
+    uint64_t id;
+    int status;    /* TF_OK */
+    int op, dtype, kind;
+    int flag;      /* 1 when the error estimate is large (see above) */
+    int64_t n;
+    double z0, z1;                 /* sum / dot result, widened to binary64 */
+    double max_abs_z0, max_abs_z1; /* axpy / Horner */
+    uint64_t n_flagged;            /* axpy / Horner: elements over threshold */
+    uint64_t nonfinite;            /* non-finite results */
+    uint64_t hash_z0, hash_z1;     /* axpy / Horner: sum of bit patterns mod 2^64 */
+    double t_arrive, t_admit, t_publish, t_done; /* seconds, tfs_clock() */
+    double device_us;              /* first claim to completion on the device */
+} tfs_result;
+
+typedef struct {
+    int64_t pending, in_flight, completed;
+    uint64_t budget_bytes, resident_bytes, peak_resident_bytes;
+    uint64_t admission_waits;      /* times the queue head waited for memory */
+    int kernel_alive;
+} tfs_stats;
+
+typedef struct tfs_server tfs_server;
+
+/* Create a server on `device` with an HBM pool of budget_bytes and at most
+ * max_slots (1 .. TFS_MAX_SLOTS) jobs in flight; launches the persistent
+ * kernel.  NULL on failure. */
+tfs_server *tfs_create(int device, uint64_t budget_bytes, int max_slots);
+
+/* Queue a job (thread-safe, non-blocking).  t_arrive: its arrival time on
+ * tfs_clock() (<= 0: now).  TF_EINVAL for a malformed job, TF_ENOMEM for a
+ * job larger than the whole budget. */
+int tfs_submit(tfs_server *s, const tfs_job *job, double t_arrive, uint64_t *id);
+
+/* Move up to `max` completed results into out[]; returns how many. */
+int tfs_poll(tfs_server *s, tfs_result *out, int max);
+
+/* Counters of the server (thread-safe). */
+int tfs_get_stats(tfs_server *s, tfs_stats *out);
+
+/* Seconds on the server clock (monotonic, process-wide). */
+double tfs_clock(void);
+
+/* Stop the persistent kernel (jobs in flight finish first is not waited
+ * for: pending jobs are dropped), free everything. */
+int tfs_destroy(tfs_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,15 +37,18 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every csrc/*.hip into libtwofold.so (always recompiles)."""
+def build(verbose: bool = False, extra_flags=(), out: str = LIB_PATH) -> str:
+    """Compile every csrc/*.hip into libtwofold.so (always recompiles).
+    ``extra_flags`` (e.g. -D tuning macros) and ``out`` build a variant of
+    the library elsewhere."""
     objs = []
-    build_dir = os.path.join(PKG, "_build")
+    tag = "" if out == LIB_PATH else "_" + os.path.basename(out).replace(".so", "")
+    build_dir = os.path.join(PKG, "_build" + tag)
     os.makedirs(build_dir, exist_ok=True)
     procs = []
     for src in sources():
         obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True)))
@@ -60,10 +63,10 @@ def build(verbose: bool = False) -> str:
             print(err, file=sys.stderr)
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join("%s:\n%s" % f for f in failed))
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs], check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -7,6 +7,23 @@
 // by the first threads of block 0; misaligned arrays take a scalar kernel.
 #include "tf_internal.hpp"
 
+// Vectors in flight per thread, tuned on MI355X at n = 2^28: binary64
+// kernels run best with one 16-byte vector per operand per thread, binary32
+// binary operations with four (the square root, with half the streams,
+// with one).
+#ifndef TF_EW_UNROLL_F64
+#define TF_EW_UNROLL_F64 1
+#endif
+#ifndef TF_EW_UNROLL_F32
+#define TF_EW_UNROLL_F32 4
+#endif
+#ifndef TF_EW_UNROLL_F32_UNARY
+#define TF_EW_UNROLL_F32_UNARY 1
+#endif
+#ifndef TF_PLAIN_UNROLL
+#define TF_PLAIN_UNROLL 4
+#endif
+
 namespace tf {
 
 // ---------------------------------------------------------------------------
@@ -78,7 +95,9 @@ __global__ __launch_bounds__(kBlock) void ew_scalar_kernel(int64_t n, const T *x
 template <typename T, int OP, bool XT, bool YT>
 static void launch_ew(const Launch &L, int64_t n, const T *x0, const T *x1, const T *y0, const T *y1,
                       T *z0, T *z1) {
-    constexpr int UNROLL = 2;
+    constexpr int UNROLL = sizeof(T) == 8 ? TF_EW_UNROLL_F64
+                           : OP == OP_SQRT ? TF_EW_UNROLL_F32_UNARY
+                                           : TF_EW_UNROLL_F32;
     if (L.aligned) {
         const int64_t nvec = n / Vec<T>::N;
         const unsigned g = grid_for(nvec, (int64_t)kBlock * UNROLL, L.cap);
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void plain_scalar_kernel(int64_t n, const T
 
 template <typename T, int OP>
 static void launch_plain(const Launch &L, int64_t n, const T *x, const T *y, T *z) {
-    constexpr int UNROLL = 4;
+    constexpr int UNROLL = TF_PLAIN_UNROLL;
     if (L.aligned) {
         const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kBlock * UNROLL, L.cap);
         hipLaunchKernelGGL((plain_vec_kernel<T, OP, UNROLL>), dim3(g), dim3(kBlock), 0, L.stream, n, x,
@@ -216,12 +235,6 @@ template void run_plain<float>(const Launch &, int, int64_t, const void *, const
 // ---------------------------------------------------------------------------
 // axpy: z = a x + y, a a twofold scalar
 // ---------------------------------------------------------------------------
-
-template <typename T, bool XT, bool YT>
-__device__ __forceinline__ Pair<T> axpy_one(T a0, T a1, T x0, T x1, T y0, T y1) {
-    const Pair<T> t = XT ? mul_tt(a0, a1, x0, x1) : mul_td(a0, a1, x0);
-    return YT ? add_tt(t.hi, t.lo, y0, y1) : add_td(t.hi, t.lo, y0);
-}
 
 template <typename T, bool XT, bool YT, int UNROLL>
 __global__ __launch_bounds__(kBlock) void axpy_vec_kernel(int64_t n, T a0, T a1, const T *x0,
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void axpy_scalar_kernel(int64_t n, T a0, T 
 template <typename T, bool XT, bool YT>
 static void launch_axpy(const Launch &L, int64_t n, T a0, T a1, const T *x0, const T *x1,
                         const T *y0, const T *y1, T *z0, T *z1) {
-    constexpr int UNROLL = 2;
+    constexpr int UNROLL = sizeof(T) == 8 ? TF_EW_UNROLL_F64 : TF_EW_UNROLL_F32;
     if (L.aligned) {
         const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kBlock * UNROLL, L.cap);
         hipLaunchKernelGGL((axpy_vec_kernel<T, XT, YT, UNROLL>), dim3(g), dim3(kBlock), 0, L.stream, n,
@@ -347,21 +360,6 @@ template void run_plain_axpy<float>(const Launch &, int64_t, const void *, const
 // ---------------------------------------------------------------------------
 // Horner: coefficients travel by value in the kernel arguments
 // ---------------------------------------------------------------------------
-
-template <typename T>
-struct Coeffs {
-    T c[TF_MAX_DEGREE + 1];
-};
-
-template <typename T, bool XT>
-__device__ __forceinline__ Pair<T> horner_one(const Coeffs<T> &C, int degree, T x0, T x1) {
-    Pair<T> r{C.c[degree], T(0)};
-    for (int k = degree - 1; k >= 0; --k) {
-        const Pair<T> m = XT ? mul_tt(r.hi, r.lo, x0, x1) : mul_td(r.hi, r.lo, x0);
-        r = add_td(m.hi, m.lo, C.c[k]);
-    }
-    return r;
-}
 
 template <typename T, bool XT>
 __global__ __launch_bounds__(kBlock) void horner_kernel(int64_t n, int degree, Coeffs<T> C, const T *x0,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tf.h"
 #include "tf_math.hpp"
 
 namespace tf {
@@ -25,13 +26,32 @@ struct Vec<float> {
     static constexpr int N = 4;
 };
 
+// Streaming data is touched once: non-temporal loads and stores keep it
+// from displacing other lines in the caches.
+#ifndef TF_NT_LOAD
+#define TF_NT_LOAD 1
+#endif
+#ifndef TF_NT_STORE
+#define TF_NT_STORE 1
+#endif
+
 template <typename T>
 __device__ __forceinline__ typename Vec<T>::type vload(const T *p, int64_t vi) {
-    return __builtin_nontemporal_load(reinterpret_cast<const typename Vec<T>::type *>(p) + vi);
+    const typename Vec<T>::type *q = reinterpret_cast<const typename Vec<T>::type *>(p) + vi;
+#if TF_NT_LOAD
+    return __builtin_nontemporal_load(q);
+#else
+    return *q;
+#endif
 }
 template <typename T>
 __device__ __forceinline__ void vstore(T *p, int64_t vi, typename Vec<T>::type v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<T>::type *>(p) + vi);
+    typename Vec<T>::type *q = reinterpret_cast<typename Vec<T>::type *>(p) + vi;
+#if TF_NT_STORE
+    __builtin_nontemporal_store(v, q);
+#else
+    *q = v;
+#endif
 }
 
 enum Op { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4 };
@@ -73,6 +93,31 @@ __device__ __forceinline__ T apply_plain(T x, T y) {
     else if constexpr (OP == OP_MUL) return x * y;
     else if constexpr (OP == OP_DIV) return x / y;
     else return sqrt_rn(x);
+}
+
+// axpy element: t = MTF1(a, x) (MTF1.1 for dotted x), z = ATF1(t, y)
+// (ATF1.1 for dotted y).
+template <typename T, bool XT, bool YT>
+__device__ __forceinline__ Pair<T> axpy_one(T a0, T a1, T x0, T x1, T y0, T y1) {
+    const Pair<T> t = XT ? mul_tt(a0, a1, x0, x1) : mul_td(a0, a1, x0);
+    return YT ? add_tt(t.hi, t.lo, y0, y1) : add_td(t.hi, t.lo, y0);
+}
+
+// Horner element: r = (c[d], +0); r = ATF1.1(MTF1(r, x), c[k]) for
+// k = d-1 .. 0 (MTF1.1 for dotted x).  Coefficients travel by value.
+template <typename T>
+struct Coeffs {
+    T c[TF_MAX_DEGREE + 1];
+};
+
+template <typename T, bool XT>
+__device__ __forceinline__ Pair<T> horner_one(const Coeffs<T> &C, int degree, T x0, T x1) {
+    Pair<T> r{C.c[degree], T(0)};
+    for (int k = degree - 1; k >= 0; --k) {
+        const Pair<T> m = XT ? mul_tt(r.hi, r.lo, x0, x1) : mul_td(r.hi, r.lo, x0);
+        r = add_td(m.hi, m.lo, C.c[k]);
+    }
+    return r;
 }
 
 // Grid for `work` items of `per_block` each, optionally capped (grid-stride

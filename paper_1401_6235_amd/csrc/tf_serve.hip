@@ -1,0 +1,558 @@
+// Serving: a persistent kernel over a device job table.
+//
+// Block 0 of the persistent grid is the dispatcher: one thread polls the
+// host-coherent descriptor ring (system-scope acquire), copies each new
+// descriptor into its device slot and opens the slot with a release store of
+// the slot's control word.  Every other block is a worker: its first wave
+// reads the 64 control words (one per lane), picks the oldest job with an
+// unclaimed unit and claims it with a compare-and-swap on the control word
+// (the generation in the word makes a stale claim fail); the whole block
+// processes the unit (a 16384-leaf aligned subtree of a sum / dot, or 16384
+// elements of an axpy / Horner), then bumps the job's done counter.  The
+// block that completes a job's last unit joins the per-unit partials and
+// writes the job's completion record (generation last, system-scope
+// release).  Workers never wait for each other, so the grid needs no
+// co-residency; every wave leaves its loop once the dispatcher has raised
+// the stop flag and no unit is left, and the dispatcher itself exits on the
+// host's stop request or after a long idle period.
+//
+// Inputs of RANDOM / ILLCOND jobs are materialised by a separate generator
+// kernel on a side stream before the job is published.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "tf_serve_host.hpp"
+#include "tf_tree.hpp"
+
+namespace tf {
+
+// ---------------------------------------------------------------------------
+// counter-based input generator (same recipe as the host test generator)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * TFS_MIX1;
+    z = (z ^ (z >> 27)) * TFS_MIX2;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t draw(uint64_t seed, int64_t i, int a) {
+    return mix64(seed + ((uint64_t)(4 * i + a) + 1) * TFS_GAMMA);
+}
+
+template <typename T>
+__device__ __forceinline__ T gen_value(uint64_t r);
+template <>
+__device__ __forceinline__ double gen_value<double>(uint64_t r) {
+    const int e = (int)((r >> 52) & 0x7ff) % 41 - 20;
+    const uint64_t bits = (r & 0x8000000000000000ull) | ((uint64_t)(1023 + e) << 52) | (r & 0xfffffffffffffull);
+    return __builtin_bit_cast(double, bits);
+}
+template <>
+__device__ __forceinline__ float gen_value<float>(uint64_t r) {
+    const int e = (int)((r >> 52) & 0x7ff) % 41 - 20;
+    const uint32_t bits = (uint32_t)((r >> 32) & 0x80000000u) | ((uint32_t)(127 + e) << 23) | (uint32_t)(r & 0x7fffffu);
+    return __builtin_bit_cast(float, bits);
+}
+// u in [-1, 1), exact
+template <typename T>
+__device__ __forceinline__ T gen_u(uint64_t r);
+template <>
+__device__ __forceinline__ double gen_u<double>(uint64_t r) { return (double)(r >> 11) * 0x1p-52 - 1.0; }
+template <>
+__device__ __forceinline__ float gen_u<float>(uint64_t r) { return (float)(uint32_t)(r >> 40) * 0x1p-23f - 1.0f; }
+// u in [0, 1), exact
+template <typename T>
+__device__ __forceinline__ T gen_u01(uint64_t r);
+template <>
+__device__ __forceinline__ double gen_u01<double>(uint64_t r) { return (double)(r >> 11) * 0x1p-53; }
+template <>
+__device__ __forceinline__ float gen_u01<float>(uint64_t r) { return (float)(uint32_t)(r >> 40) * 0x1p-24f; }
+
+template <typename T>
+__device__ __forceinline__ T low_scale();  // 2^-p
+template <>
+__device__ __forceinline__ double low_scale<double>() { return 0x1p-53; }
+template <>
+__device__ __forceinline__ float low_scale<float>() { return 0x1p-24f; }
+template <typename T>
+__device__ __forceinline__ T cancel_scale();  // relative size left after cancellation
+template <>
+__device__ __forceinline__ double cancel_scale<double>() { return 0x1p-40; }
+template <>
+__device__ __forceinline__ float cancel_scale<float>() { return 0x1p-16f; }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void gen_kernel(tfs_desc d) {
+    T *x0 = (T *)d.x0, *x1 = (T *)d.x1, *y0 = (T *)d.y0, *y1 = (T *)d.y1;
+    const uint64_t s = d.seed;
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d.n; i += step) {
+        T a;
+        if (d.op == TFS_OP_HORNER) {
+            if (d.kind == TFS_KIND_ILLCOND) a = T(1) + gen_u<T>(draw(s, i, 0)) * T(0x1p-12);
+            else a = T(0.9) + T(0.2) * gen_u01<T>(draw(s, i, 0));
+        } else {
+            a = gen_value<T>(draw(s, i, 0));
+        }
+        x0[i] = a;
+        if (x1) x1[i] = a * (gen_u<T>(draw(s, i, 1)) * low_scale<T>());
+        if (y0) {
+            T b;
+            if (d.op == TFS_OP_AXPY && d.kind == TFS_KIND_ILLCOND)
+                b = -(T(d.a0) * a) + a * (gen_u<T>(draw(s, i, 2)) * cancel_scale<T>());
+            else
+                b = gen_value<T>(draw(s, i, 2));
+            y0[i] = b;
+            if (y1) y1[i] = b * (gen_u<T>(draw(s, i, 3)) * low_scale<T>());
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// persistent kernel
+// ---------------------------------------------------------------------------
+
+struct DevSlot {
+    uint64_t ctl;   // TFS_CTL(gen, nclaims, next); 0 = empty
+    uint32_t done;  // claims finished
+    uint32_t pad;
+    uint64_t t_start;
+    tfs_desc d;
+};
+struct DevState {
+    DevSlot slot[TFS_MAX_SLOTS];
+    uint64_t stop;
+};
+
+__device__ __forceinline__ uint64_t ld_acq_sys(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_sys(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void st_rel_sys(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
+    uint64_t consumed = ld_sys(&sh->consumed);  // resume after a relaunch
+    uint64_t last = wall_clock64();
+    uint64_t beats = 0;
+    int how = 2;
+    st_rel_sys(&sh->kernel_state, 1);
+    while (true) {
+        const uint64_t pub = ld_acq_sys(&sh->pub_count);
+        const bool fresh = consumed < pub;
+        while (consumed < pub) {
+            // plain loads after the acquire above: independent, so they
+            // pipeline over the host link instead of one round trip each
+            const tfs_desc tmp = sh->ring[consumed % TFS_RING];
+            ++consumed;
+            st_rel_sys(&sh->consumed, consumed);
+            if (tmp.slot < 0 || tmp.slot >= TFS_MAX_SLOTS) continue;  // malformed entry: skip
+            DevSlot *s = &st->slot[tmp.slot];
+            s->d = tmp;
+            s->done = 0;
+            s->t_start = 0;
+            __hip_atomic_store(&s->ctl, TFS_CTL(tmp.gen, tmp.nclaims, 0), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (fresh) last = wall_clock64();
+        if (ld_acq_sys(&sh->stop)) break;
+        if (wall_clock64() - last > idle_ticks) {
+            bool busy = false;
+            for (int k = 0; k < TFS_MAX_SLOTS; ++k)
+                busy |= __hip_atomic_load(&st->slot[k].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (!busy) {
+                how = 3;
+                break;
+            }
+            last = wall_clock64();
+        }
+        if ((++beats & 1023) == 0) st_rel_sys(&sh->heartbeat, beats);
+        __builtin_amdgcn_s_sleep(16);
+    }
+    __hip_atomic_store(&st->stop, (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    st_rel_sys(&sh->kernel_state, (uint64_t)how);
+}
+
+// ---- one unit of a reduction job ---------------------------------------------
+
+template <typename T, int LEAF>
+__device__ void claim_reduce(const tfs_desc &d, int claim) {
+    const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
+    const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1) & 15u) == 0;
+    const int64_t tiles = (d.n + kTile - 1) / kTile;
+    const Pair<T> r = block_subtree<T, LEAF>(claim, d.tiles_per_claim, d.n, tiles, aligned, x0, x1, y0, y1);
+    if (threadIdx.x == 0) ((Pair<T> *)d.part)[claim] = r;
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t bits_of(T v) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(uint64_t, v);
+    else return (uint64_t)__builtin_bit_cast(uint32_t, v);
+}
+
+// Block-wide reduction of a vector unit's summary (max is exact and the
+// sums are integers, so the order does not matter); result in thread 0.
+__device__ tfs_vsum block_summary(tfs_vsum v) {
+    __shared__ tfs_vsum s[kBlock];
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            s[t].max0 = fmax(s[t].max0, s[t + w].max0);
+            s[t].max1 = fmax(s[t].max1, s[t + w].max1);
+            s[t].n_flagged += s[t + w].n_flagged;
+            s[t].nonfinite += s[t + w].nonfinite;
+            s[t].hash0 += s[t + w].hash0;
+            s[t].hash1 += s[t + w].hash1;
+        }
+        __syncthreads();
+    }
+    const tfs_vsum r = s[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void account(tfs_vsum &acc, T z0, T z1, double thr) {
+    const double a0 = fabs((double)z0), a1 = fabs((double)z1);
+    const bool finite = isfinite(z0) && isfinite(z1);
+    acc.max0 = fmax(acc.max0, a0);
+    acc.max1 = fmax(acc.max1, a1);
+    acc.nonfinite += finite ? 0 : 1;
+    acc.n_flagged += (!finite || a1 > thr * a0) ? 1 : 0;
+    acc.hash0 += bits_of(z0);
+    acc.hash1 += bits_of(z1);
+}
+
+// ---- one unit of an axpy / Horner job ----------------------------------------
+
+template <typename T, int OP, bool XT, bool YT>
+__device__ void claim_vector(const tfs_desc &d, int claim) {
+    const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
+    T *z0 = (T *)d.z0, *z1 = (T *)d.z1;
+    const int64_t base = (int64_t)claim * TFS_CLAIM;
+    const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
+    tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
+    Coeffs<T> C;
+    if constexpr (OP == TFS_OP_HORNER)
+        for (int k = 0; k <= d.degree; ++k) C.c[k] = (T)d.c[k];
+    const T a0 = (T)d.a0, a1 = (T)d.a1;
+    for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+        Pair<T> z;
+        if constexpr (OP == TFS_OP_AXPY) z = axpy_one<T, XT, YT>(a0, a1, x0[i], XT ? x1[i] : T(0), y0[i], YT ? y1[i] : T(0));
+        else z = horner_one<T, XT>(C, d.degree, x0[i], XT ? x1[i] : T(0));
+        z0[i] = z.hi;
+        z1[i] = z.lo;
+        account(acc, z.hi, z.lo, d.thr);
+    }
+    const tfs_vsum r = block_summary(acc);
+    if (threadIdx.x == 0) ((tfs_vsum *)d.part)[claim] = r;
+}
+
+template <typename T>
+__device__ void run_claim(const tfs_desc &d, int claim) {
+    const bool xt = d.x1 != 0, yt = d.y1 != 0;
+    switch (d.op) {
+    case TFS_OP_SUM:
+        if (xt) claim_reduce<T, LEAF_SUM_T>(d, claim);
+        else claim_reduce<T, LEAF_SUM_D>(d, claim);
+        break;
+    case TFS_OP_DOT:
+        if (xt && yt) claim_reduce<T, LEAF_DOT_TT>(d, claim);
+        else if (xt) claim_reduce<T, LEAF_DOT_TD>(d, claim);
+        else if (yt) claim_reduce<T, LEAF_DOT_DT>(d, claim);
+        else claim_reduce<T, LEAF_DOT_DD>(d, claim);
+        break;
+    case TFS_OP_AXPY:
+        if (xt && yt) claim_vector<T, TFS_OP_AXPY, true, true>(d, claim);
+        else if (xt) claim_vector<T, TFS_OP_AXPY, true, false>(d, claim);
+        else if (yt) claim_vector<T, TFS_OP_AXPY, false, true>(d, claim);
+        else claim_vector<T, TFS_OP_AXPY, false, false>(d, claim);
+        break;
+    default:
+        if (xt) claim_vector<T, TFS_OP_HORNER, true, false>(d, claim);
+        else claim_vector<T, TFS_OP_HORNER, false, false>(d, claim);
+    }
+}
+
+// ---- completion ------------------------------------------------------------------
+
+template <typename T>
+__device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
+    tfs_done out = {};
+    if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
+        const int padded = d.padded;
+        const int group = padded > kBlock ? padded / kBlock : 1;
+        const int active = padded / group;
+        const Pair<T> r = block_join<T, false>(0, d.nclaims, group, active, (const Pair<T> *)d.part);
+        const double z0 = (double)r.hi, z1 = (double)r.lo;
+        out.z0 = z0;
+        out.z1 = z1;
+        const bool finite = isfinite(z0) && isfinite(z1);
+        out.nonfinite = finite ? 0 : 1;
+        out.flag = (!finite || fabs(z1) > d.thr * fabs(z0)) ? 1 : 0;
+    } else {
+        tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
+        const tfs_vsum *p = (const tfs_vsum *)d.part;
+        for (int k = threadIdx.x; k < d.nclaims; k += kBlock) {
+            acc.max0 = fmax(acc.max0, p[k].max0);
+            acc.max1 = fmax(acc.max1, p[k].max1);
+            acc.n_flagged += p[k].n_flagged;
+            acc.nonfinite += p[k].nonfinite;
+            acc.hash0 += p[k].hash0;
+            acc.hash1 += p[k].hash1;
+        }
+        const tfs_vsum r = block_summary(acc);
+        out.max0 = r.max0;
+        out.max1 = r.max1;
+        out.n_flagged = r.n_flagged;
+        out.nonfinite = r.nonfinite;
+        out.hash0 = r.hash0;
+        out.hash1 = r.hash1;
+        out.flag = (r.nonfinite > 0 || r.max1 > d.thr * r.max0) ? 1 : 0;
+    }
+    if (threadIdx.x == 0) {
+        // empty the slot first: the host reuses it only after seeing the record
+        __hip_atomic_store(&S->ctl, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        out.t_start = S->t_start;
+        out.t_end = wall_clock64();
+        out.status = TF_OK;
+        rec->status = out.status;
+        rec->flag = out.flag;
+        rec->z0 = out.z0;
+        rec->z1 = out.z1;
+        rec->max0 = out.max0;
+        rec->max1 = out.max1;
+        rec->n_flagged = out.n_flagged;
+        rec->nonfinite = out.nonfinite;
+        rec->hash0 = out.hash0;
+        rec->hash1 = out.hash1;
+        rec->t_start = out.t_start;
+        rec->t_end = out.t_end;
+        st_rel_sys(&rec->gen, d.gen);
+    }
+}
+
+__device__ void worker(tfs_shared *sh, DevState *st) {
+    __shared__ int s_slot, s_claim, s_last;
+    __shared__ uint64_t s_desc[sizeof(tfs_desc) / 8];
+    const int t = threadIdx.x;
+    while (true) {
+        if (t < 64) {
+            const uint64_t c = __hip_atomic_load(&st->slot[t].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t gen = TFS_CTL_GEN(c);
+            const uint64_t key = (gen != 0 && TFS_CTL_NEXT(c) < TFS_CTL_NTILES(c)) ? gen : ~0ull;
+            uint64_t m = key;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t o = __shfl_xor(m, d);
+                m = o < m ? o : m;
+            }
+            if (m == ~0ull) {
+                if (t == 0) {
+                    const bool stop = __hip_atomic_load(&st->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                    s_slot = stop ? -3 : -1;
+                }
+            } else if (key == m) {  // the one lane holding the oldest open job
+                uint64_t expected = c;
+                const bool ok = __hip_atomic_compare_exchange_strong(
+                    &st->slot[t].ctl, &expected, c + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_slot = ok ? t : -2;
+                s_claim = (int)TFS_CTL_NEXT(c);
+            }
+        }
+        __syncthreads();
+        const int slot = s_slot, claim = s_claim;
+        __syncthreads();
+        if (slot == -3) break;
+        if (slot < 0) {
+            if (slot == -1) __builtin_amdgcn_s_sleep(64);
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        DevSlot *S = &st->slot[slot];
+        const uint64_t *src = (const uint64_t *)&S->d;
+        for (unsigned k = t; k < sizeof(tfs_desc) / 8; k += kBlock) s_desc[k] = src[k];
+        __syncthreads();
+        const tfs_desc &d = *(const tfs_desc *)s_desc;
+        if (claim == 0 && t == 0) S->t_start = wall_clock64();
+        if (d.dtype == TF_F64) run_claim<double>(d, claim);
+        else run_claim<float>(d, claim);
+        __syncthreads();
+        if (t == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t done = __hip_atomic_fetch_add(&S->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = done + 1 == (uint32_t)d.nclaims;
+        }
+        __syncthreads();
+        if (s_last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (d.dtype == TF_F64) finalize<double>(d, S, &sh->done[slot]);
+            else finalize<float>(d, S, &sh->done[slot]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void serve_kernel(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) dispatcher(sh, st, idle_ticks);
+        return;
+    }
+    worker(sh, st);
+}
+
+// ---------------------------------------------------------------------------
+// HIP implementation of the server's device interface
+// ---------------------------------------------------------------------------
+
+class HipDevice : public tfs::DeviceOps {
+  public:
+    int init(int device, uint64_t budget) {
+        device_ = device;
+        if (hipSetDevice(device) != hipSuccess) return TF_EDEVICE;
+        if (budget && hipMalloc(&pool_, budget) != hipSuccess) return TF_ENOMEM;
+        if (hipHostMalloc((void **)&shared_, sizeof(tfs_shared), hipHostMallocCoherent | hipHostMallocMapped) !=
+            hipSuccess)
+            return TF_ENOMEM;
+        memset(shared_, 0, sizeof(tfs_shared));
+        if (hipMalloc(&state_, sizeof(DevState)) != hipSuccess) return TF_ENOMEM;
+        if (hipMemset(state_, 0, sizeof(DevState)) != hipSuccess) return TF_EDEVICE;
+        if (hipStreamCreateWithFlags(&work_, hipStreamNonBlocking) != hipSuccess) return TF_EDEVICE;
+        if (hipStreamCreateWithFlags(&gen_, hipStreamNonBlocking) != hipSuccess) return TF_EDEVICE;
+        int rate_khz = 100000, cus = 256;
+        (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+        tick_hz_ = (double)rate_khz * 1000.0;
+        workers_ = cus;
+        events_.resize(2 * TFS_MAX_SLOTS);
+        for (auto &e : events_) {
+            if (hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess) return TF_EDEVICE;
+            e.used = false;
+        }
+        return TF_OK;
+    }
+    ~HipDevice() override {
+        if (device_ >= 0) (void)hipSetDevice(device_);
+        if (work_) (void)hipStreamSynchronize(work_);
+        if (gen_) (void)hipStreamSynchronize(gen_);
+        for (auto &e : events_)
+            if (e.ev) (void)hipEventDestroy(e.ev);
+        if (work_) (void)hipStreamDestroy(work_);
+        if (gen_) (void)hipStreamDestroy(gen_);
+        if (state_) (void)hipFree(state_);
+        if (shared_) (void)hipHostFree(shared_);
+        if (pool_) (void)hipFree(pool_);
+    }
+    uint64_t pool_base() override { return (uint64_t)pool_; }
+    tfs_shared *shared() override { return shared_; }
+    double tick_hz() const { return tick_hz_; }
+    int start() override {
+        (void)hipSetDevice(device_);
+        __atomic_store_n(&shared_->stop, 0, __ATOMIC_RELEASE);
+        const uint64_t zero = 0;
+        if (hipMemcpy(&state_->stop, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return TF_EDEVICE;
+        const uint64_t idle = (uint64_t)(30.0 * tick_hz_);  // drain after 30 s without work
+        hipLaunchKernelGGL(serve_kernel, dim3(1 + workers_), dim3(kBlock), 0, work_, shared_, state_, idle);
+        return hipGetLastError() == hipSuccess ? TF_OK : TF_EDEVICE;
+    }
+    bool running() override { return hipStreamQuery(work_) == hipErrorNotReady; }
+    int stop() override {
+        __atomic_store_n(&shared_->stop, 1, __ATOMIC_RELEASE);
+        return hipStreamSynchronize(work_) == hipSuccess ? TF_OK : TF_EDEVICE;
+    }
+    int materialize(const tfs_desc &d, int *token) override {
+        int k = -1;
+        for (size_t i = 0; i < events_.size(); ++i)
+            if (!events_[i].used) {
+                k = (int)i;
+                break;
+            }
+        if (k < 0) return TF_EBUSY;
+        events_[k].used = true;
+        int64_t blocks = (d.n + kBlock - 1) / kBlock;
+        if (blocks > 8 * workers_) blocks = 8 * workers_;
+        if (d.dtype == TF_F64) hipLaunchKernelGGL(gen_kernel<double>, dim3((unsigned)blocks), dim3(kBlock), 0, gen_, d);
+        else hipLaunchKernelGGL(gen_kernel<float>, dim3((unsigned)blocks), dim3(kBlock), 0, gen_, d);
+        (void)hipEventRecord(events_[k].ev, gen_);
+        *token = k;
+        return TF_OK;
+    }
+    bool materialized(int token) override { return hipEventQuery(events_[token].ev) == hipSuccess; }
+    void release_token(int token) override { events_[token].used = false; }
+
+  private:
+    struct Ev {
+        hipEvent_t ev = nullptr;
+        bool used = false;
+    };
+    int device_ = -1;
+    void *pool_ = nullptr;
+    tfs_shared *shared_ = nullptr;
+    DevState *state_ = nullptr;
+    hipStream_t work_ = nullptr, gen_ = nullptr;
+    std::vector<Ev> events_;
+    double tick_hz_ = 1e8;
+    int workers_ = 256;
+};
+
+}  // namespace tf
+
+struct tfs_server {
+    tf::HipDevice dev;
+    tfs::Server *server = nullptr;
+};
+
+extern "C" {
+
+double tfs_clock(void) { return tfs::now_s(); }
+
+tfs_server *tfs_create(int device, uint64_t budget_bytes, int max_slots) {
+    if (max_slots < 1 || max_slots > TFS_MAX_SLOTS || budget_bytes < 4096) return nullptr;
+    tfs_server *s = new (std::nothrow) tfs_server;
+    if (!s) return nullptr;
+    if (s->dev.init(device, budget_bytes) != TF_OK) {
+        delete s;
+        return nullptr;
+    }
+    s->server = new tfs::Server(&s->dev, budget_bytes, max_slots);
+    if (s->server->start() != TF_OK) {
+        delete s->server;
+        delete s;
+        return nullptr;
+    }
+    return s;
+}
+
+int tfs_submit(tfs_server *s, const tfs_job *job, double t_arrive, uint64_t *id) {
+    if (!s || !job) return TF_EINVAL;
+    return s->server->submit(*job, t_arrive, id);
+}
+
+int tfs_poll(tfs_server *s, tfs_result *out, int max) {
+    if (!s || !out || max < 0) return TF_EINVAL;
+    return s->server->poll(out, max);
+}
+
+int tfs_get_stats(tfs_server *s, tfs_stats *out) {
+    if (!s || !out) return TF_EINVAL;
+    s->server->stats(out);
+    return TF_OK;
+}
+
+int tfs_destroy(tfs_server *s) {
+    if (!s) return TF_EINVAL;
+    s->server->shutdown();
+    delete s->server;
+    delete s;
+    return TF_OK;
+}
+
+}  // extern "C"

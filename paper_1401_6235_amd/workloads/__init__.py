@@ -249,3 +249,121 @@ def exact_dot_f64(x, y) -> float:
     x = np.ascontiguousarray(x, np.float64)
     y = np.ascontiguousarray(y, np.float64)
     return float(_gen_lib().tfgen_exact_dot_f64(C.c_int64(x.size), _ptr(x), _ptr(y)))
+
+
+# ---------------------------------------------------------------------------
+# Serving jobs: the counter-based generator the device uses for RANDOM and
+# ILLCOND jobs, implemented again here from its published definition
+# (SplitMix64: Steele, Lea and Flood 2014, with the finaliser constants of
+# Vigna's splitmix64), so that a job's inputs can be rebuilt on the host
+# bit for bit.  Element i of array a (0: x0, 1: x1, 2: y0, 3: y1) draws
+# mix(seed + (4 i + a + 1) * gamma).
+# ---------------------------------------------------------------------------
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix64(z):
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _MIX1
+        z = (z ^ (z >> np.uint64(27))) * _MIX2
+    return z ^ (z >> np.uint64(31))
+
+
+def serve_draw(seed: int, n: int, a: int):
+    i = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        k = i * np.uint64(4) + np.uint64(a + 1)
+        return _mix64(np.uint64(seed) + k * _GAMMA)
+
+
+def _serve_value(r, dtype):
+    e = ((r >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64) % 41 - 20
+    if dtype == F64:
+        bits = (r & np.uint64(0x8000000000000000)) | ((e + 1023).astype(np.uint64) << np.uint64(52)) \
+            | (r & np.uint64(0xFFFFFFFFFFFFF))
+        return bits.view(np.float64)
+    bits = ((r >> np.uint64(32)) & np.uint64(0x80000000)) | ((e + 127).astype(np.uint64) << np.uint64(23)) \
+        | (r & np.uint64(0x7FFFFF))
+    return bits.astype(np.uint32).view(np.float32)
+
+
+def _serve_u(r, dtype):
+    if dtype == F64:
+        return (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+    return (r >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -23) - np.float32(1.0)
+
+
+def _serve_u01(r, dtype):
+    if dtype == F64:
+        return (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return (r >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)
+
+
+def serve_inputs(op: str, dtype, n: int, seed: int, kind: str = "random", a0: float = 0.7):
+    """Inputs of a RANDOM / ILLCOND serving job, as the device generates them.
+
+    sum: twofold leaves (x0, x1); dot: plain x0, y0; axpy: twofold x, y
+    (ILLCOND: y0 = -(a0 x0) + x0 (u 2^-40), 2^-16 in binary32, so that
+    a x + y cancels); Horner: twofold x with x0 = 0.9 + 0.2 u01 (ILLCOND:
+    x0 = 1 + u 2^-12).  Low parts are x1 = x0 (u 2^-p).
+    """
+    dtype = np.dtype(dtype)
+    t = dtype.type
+    low = t(2.0 ** -53) if dtype == F64 else t(2.0 ** -24)
+    r0 = serve_draw(seed, n, 0)
+    if op == "horner":
+        if kind == "illcond":
+            x0 = t(1) + _serve_u(r0, dtype) * t(2.0 ** -12)
+        else:
+            x0 = t(0.9) + t(0.2) * _serve_u01(r0, dtype)
+    else:
+        x0 = _serve_value(r0, dtype)
+    out = {"x0": x0}
+    if op in ("sum", "axpy", "horner"):
+        out["x1"] = x0 * (_serve_u(serve_draw(seed, n, 1), dtype) * low)
+    if op in ("dot", "axpy"):
+        r2 = serve_draw(seed, n, 2)
+        if op == "axpy" and kind == "illcond":
+            cs = t(2.0 ** -40) if dtype == F64 else t(2.0 ** -16)
+            a = t(a0)
+            y0 = -(a * x0) + x0 * (_serve_u(r2, dtype) * cs)
+        else:
+            y0 = _serve_value(r2, dtype)
+        out["y0"] = y0
+        if op == "axpy":
+            out["y1"] = y0 * (_serve_u(serve_draw(seed, n, 3), dtype) * low)
+    return out
+
+
+HORNER_ILLCOND_C = [1.0, -8.0, 28.0, -56.0, 70.0, -56.0, 28.0, -8.0, 1.0]  # (x - 1)^8
+
+
+def serve_schedule(jobs: int, rate: float, seed: int = 1, min_log2: int = 8, max_log2: int = 24,
+                   illcond_frac: float = 0.05):
+    """The serving stream: Poisson arrivals at `rate` jobs/s; type uniform
+    over sum / dot / axpy / Horner-8; length floor(2^(min + (max - min) U));
+    binary32 or binary64 with probability 1/2; a fraction `illcond_frac`
+    of ill-conditioned jobs.  Draw order in stream (seed, 6): gaps, types,
+    dtypes, lengths, ill-conditioned marks, job seeds, Horner coefficient
+    sets."""
+    g = rng(seed, 6)
+    gaps = g.exponential(1.0 / rate, jobs)
+    types = g.integers(0, 4, jobs)
+    dts = g.integers(0, 2, jobs)
+    lens = np.floor(2.0 ** (min_log2 + (max_log2 - min_log2) * g.random(jobs))).astype(np.int64)
+    ill = g.random(jobs) < illcond_frac
+    seeds = g.integers(0, 2 ** 63, jobs, dtype=np.int64)
+    coeffs = g.uniform(-1.0, 1.0, (jobs, 9))
+    coeffs[:, 1] = 0.0
+    names = ["sum", "dot", "axpy", "horner"]
+    out = []
+    t = 0.0
+    for k in range(jobs):
+        t += gaps[k]
+        out.append({"t": t, "op": names[types[k]], "dtype": "f64" if dts[k] else "f32",
+                    "n": int(lens[k]), "illcond": bool(ill[k]), "seed": int(seeds[k]),
+                    "c": coeffs[k].tolist()})
+    return out

@@ -1,0 +1,262 @@
+"""GPU serving: the persistent kernel over the device job table.
+
+Every result is checked against the oracle on inputs rebuilt on the host
+with the same counter-based generator (an independent implementation of
+its published definition): sum / dot (z0, z1) bit for bit; axpy / Horner
+the maximum |z0|, |z1|, the flagged-element count and the digests of z0 and
+z1, all exact.  Also: a job's result is identical alone and inside a mix of
+concurrent jobs; a Poisson stream agrees with the oracle on every job and
+flag; a budget far below the offered load forces admission waits and still
+completes every job.
+"""
+import struct
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import step, to_gpu, torch_cuda
+from paper_1401_6235_amd import serve as S
+from paper_1401_6235_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THR = 2.0 ** -20
+NP = {"f32": np.float32, "f64": np.float64}
+
+
+def bits64(x: float) -> int:
+    return struct.unpack("<Q", struct.pack("<d", float(x)))[0]
+
+
+def same_double(a, b) -> bool:
+    if np.isnan(a) and np.isnan(b):
+        return True
+    return bits64(a) == bits64(b)
+
+
+def expected(job: dict):
+    """Oracle result of one job (dict with op, dtype, n, seed, illcond, c)."""
+    dt = NP[job["dtype"]]
+    kind = "illcond" if job.get("illcond") and job["op"] in ("axpy", "horner") else "random"
+    if job.get("provided") is not None:
+        x = job["provided"]
+        if job["op"] == "dot":
+            z = oracle.dot(x["x0"], None, x["y0"], None)
+        else:
+            z = oracle.sum(x["x0"], x["x1"])
+        return scalar_summary(z)
+    x = W.serve_inputs(job["op"], dt, job["n"], job["seed"], kind)
+    if job["op"] == "sum":
+        return scalar_summary(oracle.sum(x["x0"], x["x1"]))
+    if job["op"] == "dot":
+        return scalar_summary(oracle.dot(x["x0"], None, x["y0"], None))
+    if job["op"] == "axpy":
+        a = np.array([0.7, 1e-17], dt)
+        z0, z1 = oracle.axpy(a, x["x0"], x["x1"], x["y0"], x["y1"])
+    else:
+        c = np.array(job_coeffs(job), dt)
+        z0, z1 = oracle.horner(c, x["x0"], x["x1"])
+    return vector_summary(z0, z1)
+
+
+def job_coeffs(job):
+    if job.get("illcond") and job["op"] == "horner":
+        return W.HORNER_ILLCOND_C
+    return job["c"]
+
+
+def scalar_summary(z):
+    z0, z1 = float(z[0]), float(z[1])
+    finite = np.isfinite(z0) and np.isfinite(z1)
+    return {"z0": z0, "z1": z1, "flag": int((not finite) or abs(z1) > THR * abs(z0)),
+            "nonfinite": int(not finite)}
+
+
+def vector_summary(z0, z1):
+    a0 = np.abs(z0.astype(np.float64))
+    a1 = np.abs(z1.astype(np.float64))
+    finite = np.isfinite(z0) & np.isfinite(z1)
+    ui = np.uint64 if z0.dtype == np.float64 else np.uint32
+    h0 = int(z0.view(ui).astype(np.uint64).sum(dtype=np.uint64))
+    h1 = int(z1.view(ui).astype(np.uint64).sum(dtype=np.uint64))
+    m0, m1 = float(np.fmax.reduce(a0)), float(np.fmax.reduce(a1))
+    nonfinite = int((~finite).sum())
+    flagged = int(((~finite) | (a1 > THR * a0)).sum())
+    return {"max_abs_z0": m0, "max_abs_z1": m1, "n_flagged": flagged, "nonfinite": nonfinite,
+            "hash_z0": h0, "hash_z1": h1, "flag": int(nonfinite > 0 or m1 > THR * m0)}
+
+
+def check(res: dict, exp: dict, what=""):
+    for k, v in exp.items():
+        if isinstance(v, float):
+            assert same_double(res[k], v), (what, k, res[k], v)
+        else:
+            assert res[k] == v, (what, k, res[k], v)
+
+
+def make(job):
+    kind = S.TFS_KIND_RANDOM
+    if job.get("illcond") and job["op"] in ("axpy", "horner"):
+        kind = S.TFS_KIND_ILLCOND
+    c = job_coeffs(job) if job["op"] == "horner" else None
+    if job.get("provided") is not None:
+        g = job["provided_gpu"]
+        return S.make_job(job["op"], job["dtype"], job["n"], kind=S.TFS_KIND_PROVIDED,
+                          x0=g["x0"], x1=g.get("x1"), y0=g.get("y0"))
+    return S.make_job(job["op"], job["dtype"], job["n"], seed=job["seed"], kind=kind, c=c)
+
+
+def wait_all(srv, count, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < count and time.time() - t0 < timeout:
+        for r in srv.poll():
+            out[r["id"]] = r
+        time.sleep(0.0005)
+    assert len(out) == count, "only %d of %d jobs completed" % (len(out), count)
+    return out
+
+
+def run_alone(srv, job):
+    jid = srv.submit(make(job), keep=job.get("provided_gpu"))
+    return wait_all(srv, 1)[jid]
+
+
+SIZES = [1, 255, 256, 16384, 16385, 100003, 1 << 20]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_single_jobs_match_oracle(dtype):
+    torch_cuda()
+    srv = S.Server(0, 4 << 30, 64)
+    try:
+        rng = np.random.default_rng(1)
+        for op in ("sum", "dot", "axpy", "horner"):
+            for n in SIZES:
+                for ill in ((False, True) if op in ("axpy", "horner") else (False,)):
+                    job = {"op": op, "dtype": dtype, "n": n, "seed": int(rng.integers(1 << 62)),
+                           "illcond": ill, "c": rng.uniform(-1, 1, 9).tolist()}
+                    step("serve alone %s %s n=%d ill=%d" % (op, dtype, n, ill))
+                    r = run_alone(srv, job)
+                    assert r["status"] == 0
+                    check(r, expected(job), "%s %s %d" % (op, dtype, n))
+                    if ill and n >= 256:
+                        assert r["flag"] == 1
+    finally:
+        srv.close()
+
+
+def test_provided_ill_conditioned_instances_flag():
+    torch_cuda()
+    srv = S.Server(0, 1 << 30, 8)
+    try:
+        for dtype in ("f64", "f32"):
+            for n in (4096, 1 << 16):
+                d = W.illdot_case(n, 1e20, seed=3, dtype=NP[dtype])
+                hi, lo = W.product_split(d["x"], d["y"])
+                for op in ("dot", "sum"):
+                    host = {"x0": d["x"], "y0": d["y"]} if op == "dot" else {"x0": hi, "x1": lo}
+                    job = {"op": op, "dtype": dtype, "n": n, "provided": host,
+                           "provided_gpu": {k: to_gpu(v) for k, v in host.items()}}
+                    step("serve provided %s %s n=%d" % (op, dtype, n))
+                    r = run_alone(srv, job)
+                    check(r, expected(job), op)
+                    assert r["flag"] == 1   # cond 1e20 is far beyond what the twofold tracks
+    finally:
+        srv.close()
+
+
+def random_jobs(count, seed, max_log2=20):
+    rng = np.random.default_rng(seed)
+    ops = ["sum", "dot", "axpy", "horner"]
+    jobs = []
+    for _ in range(count):
+        op = ops[rng.integers(4)]
+        jobs.append({"op": op, "dtype": "f64" if rng.integers(2) else "f32",
+                     "n": int(2 ** (8 + (max_log2 - 8) * rng.random())),
+                     "seed": int(rng.integers(1 << 62)), "illcond": bool(rng.random() < 0.1),
+                     "c": rng.uniform(-1, 1, 9).tolist()})
+    return jobs
+
+
+def test_mix_equals_alone():
+    torch_cuda()
+    jobs = random_jobs(300, 11)
+    srv = S.Server(0, 8 << 30, 64)
+    try:
+        step("serve mix of %d jobs" % len(jobs))
+        ids = [srv.submit(make(j)) for j in jobs]
+        got = wait_all(srv, len(jobs))
+        peak = srv.stats()
+        for k in range(0, len(jobs), 7):
+            step("serve alone #%d" % k)
+            alone = run_alone(srv, jobs[k])
+            mixed = got[ids[k]]
+            for f in ("z0", "z1", "max_abs_z0", "max_abs_z1"):
+                assert same_double(alone[f], mixed[f]), (k, f)
+            for f in ("n_flagged", "nonfinite", "hash_z0", "hash_z1", "flag", "status"):
+                assert alone[f] == mixed[f], (k, f)
+        for k in range(0, len(jobs), 13):
+            check(got[ids[k]], expected(jobs[k]), "mix #%d" % k)
+        assert peak["completed"] >= len(jobs)
+    finally:
+        srv.close()
+
+
+def test_poisson_stream_agrees_with_oracle():
+    """1000 jobs arriving at 2000 jobs/s (lengths 2^8 .. 2^18, 5 %
+    ill-conditioned): every result and flag equals the oracle's."""
+    torch_cuda()
+    sched = W.serve_schedule(1000, 2000.0, seed=5, max_log2=18)
+    srv = S.Server(0, 8 << 30, 64)
+    try:
+        step("serve poisson stream 1000 jobs")
+        t0 = S.tfs_clock()
+        ids = []
+        for j in sched:
+            while S.tfs_clock() - t0 < j["t"]:
+                pass
+            ids.append(srv.submit(make(j), t_arrive=t0 + j["t"]))
+        got = wait_all(srv, len(sched))
+    finally:
+        srv.close()
+    lat = np.array([got[i]["t_done"] - got[i]["t_arrive"] for i in ids])
+    step("p50 %.1f us p99 %.1f us" % (np.percentile(lat, 50) * 1e6, np.percentile(lat, 99) * 1e6))
+    flags = 0
+    for j, i in zip(sched, ids):
+        check(got[i], expected(j), "stream")
+        flags += got[i]["flag"]
+    assert flags >= 1
+
+
+def test_tight_budget_forces_waits():
+    torch_cuda()
+    jobs = random_jobs(120, 21, max_log2=18)
+    srv = S.Server(0, 16 << 20, 64)
+    try:
+        step("serve tight budget")
+        for j in jobs:
+            srv.submit(make(j))
+        got = wait_all(srv, len(jobs))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["admission_waits"] > 0
+    assert st["peak_resident_bytes"] <= 16 << 20
+    assert all(r["status"] == 0 for r in got.values())
+
+
+def test_malformed_jobs_are_rejected():
+    torch_cuda()
+    srv = S.Server(0, 1 << 20, 4)
+    try:
+        with pytest.raises(Exception):
+            srv.submit(S.make_job("sum", "f64", 0))
+        with pytest.raises(Exception):
+            srv.submit(S.make_job("axpy", "f64", 1 << 22))   # larger than the budget
+        with pytest.raises(Exception):
+            srv.submit(S.make_job("dot", "f64", 100, kind=S.TFS_KIND_PROVIDED))
+    finally:
+        srv.close()
