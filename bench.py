@@ -8,7 +8,9 @@ synthetic inputs, binary64 and binary32:
     Horner, degree 8                                     n = 2^28
     sum (twofold leaves), dot (plain vectors)            n = 2^26, cond 1e16
 The same pass with the plain (non-twofold) kernels and the memory probe is
-timed right after, for the twofold/plain slowdown.  value = twofold
+timed right after, for the twofold/plain slowdown.  Then the serving stream
+runs (20,000 verification jobs at 2,000 jobs/s on the persistent kernel) and
+reports p50 / p99 latency, throughput and flag counts.  value = twofold
 elements per second over the step (input elements for the reductions).
 
 Per-kernel durations come from HIP events on the launch stream around each
@@ -216,13 +218,205 @@ def cpu_baseline(W, seconds_target=15.0):
                       "binary64 and binary32, on n = 2^20 elements each, single thread, %.1f s" % t_total}
 
 
+def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
+    """The verification-job stream on the persistent kernel: Poisson
+    arrivals, sum / dot / axpy / Horner-8 of log-uniform lengths 2^8 .. 2^24,
+    half binary32, 5 % ill-conditioned (sum / dot: instances of the
+    ill-conditioned dot generator at condition number 1e20, uploaded before
+    the clock starts, length rounded to a power of two; axpy / Horner:
+    cancelling inputs generated on the device).  Latency = completion seen
+    by the host - scheduled arrival."""
+    import numpy as np
+    from paper_1401_6235_amd import serve as S
+
+    sched = W.serve_schedule(jobs, rate, seed=seed)
+    # ill-conditioned instances, one per (length, dtype, op)
+    inst = {}
+    for j in sched:
+        if j["illcond"] and j["op"] in ("sum", "dot"):
+            n2 = 1 << int(round(np.log2(j["n"])))
+            n2 = min(max(n2, 256), 1 << 24)
+            j["n"] = n2
+            inst.setdefault((n2, j["dtype"]), None)
+    log("serving: generating %d ill-conditioned instances" % len(inst))
+    dev = "cuda"
+    for (n2, dt) in sorted(inst):
+        npdt = np.float64 if dt == "f64" else np.float32
+        d = W.illdot_case(n2, 1e20, seed=n2, dtype=npdt)
+        hi, lo = W.product_split(d["x"], d["y"])
+        inst[(n2, dt)] = {k: torch.from_numpy(v).to(dev) for k, v in
+                          (("x", d["x"]), ("y", d["y"]), ("hi", hi), ("lo", lo))}
+
+    def job_of(j):
+        if j["illcond"] and j["op"] in ("sum", "dot"):
+            t = inst[(j["n"], j["dtype"])]
+            if j["op"] == "dot":
+                return S.make_job("dot", j["dtype"], j["n"], kind=S.TFS_KIND_PROVIDED, x0=t["x"], y0=t["y"])
+            return S.make_job("sum", j["dtype"], j["n"], kind=S.TFS_KIND_PROVIDED, x0=t["hi"], x1=t["lo"])
+        kind = S.TFS_KIND_ILLCOND if j["illcond"] else S.TFS_KIND_RANDOM
+        c = (W.HORNER_ILLCOND_C if j["illcond"] else j["c"]) if j["op"] == "horner" else None
+        return S.make_job(j["op"], j["dtype"], j["n"], seed=j["seed"], kind=kind, c=c)
+
+    descs = [job_of(j) for j in sched]
+    torch.cuda.synchronize()
+    srv = S.Server(0, budget, S.TFS_MAX_SLOTS)
+    results = {}
+    try:
+        log("serving: %d jobs at %.0f jobs/s" % (jobs, rate))
+        t0 = S.tfs_clock() + 0.05
+        ids = []
+        for j, desc in zip(sched, descs):
+            ta = t0 + j["t"]
+            while S.tfs_clock() < ta:
+                pass
+            ids.append(srv.submit(desc, t_arrive=ta))
+            for r in srv.poll():
+                results[r["id"]] = r
+        deadline = time.time() + 120
+        while len(results) < jobs and time.time() < deadline:
+            for r in srv.poll():
+                results[r["id"]] = r
+            time.sleep(0.001)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    res = [results[i] for i in ids if i in results]
+    lat = np.array([r["t_done"] - r["t_arrive"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_arrive"] for r in res)
+    elems = sum(r["n"] for r in res)
+    flags = {}
+    agree = {"illcond_flagged": 0, "illcond": 0, "random_flagged": 0, "random": 0}
+    for j, i in zip(sched, ids):
+        r = results.get(i)
+        if r is None:
+            continue
+        key = "%s_%s%s" % (j["op"], j["dtype"], "_ill" if j["illcond"] else "")
+        f = flags.setdefault(key, [0, 0])
+        f[0] += 1
+        f[1] += r["flag"]
+        if j["illcond"]:
+            agree["illcond"] += 1
+            agree["illcond_flagged"] += r["flag"]
+        else:
+            agree["random"] += 1
+            agree["random_flagged"] += r["flag"]
+    return {
+        "jobs": jobs, "completed": len(res), "rate_offered": rate,
+        "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
+        "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
+        "mean_us": round(float(lat.mean()) * 1e6, 1),
+        "jobs_per_s": round(len(res) / span, 1),
+        "gelem_s": round(elems / span / 1e9, 3),
+        "device_us_p50": round(float(np.percentile([r["device_us"] for r in res], 50)), 1),
+        "peak_resident_gib": round(stats["peak_resident_bytes"] / 2 ** 30, 3),
+        "budget_gib": budget / 2 ** 30,
+        "admission_waits": stats["admission_waits"],
+        "flags_by_job": {k: {"jobs": v[0], "flagged": v[1]} for k, v in sorted(flags.items())},
+        "flag_summary": agree,
+        "status_ok": all(r["status"] == 0 for r in res),
+    }
+
+
+# rocprofv3 kernel names -> bench keys
+_OPS = {"0": "add", "1": "sub", "2": "mul", "3": "div", "4": "sqrt"}
+
+
+def bench_key(name: str):
+    import re
+    t = "f64" if "<double" in name else "f32" if "<float" in name else None
+    if t is None:
+        return None
+    m = re.search(r"ew_vec_kernel<\w+, (\d), true, (true|false)", name)
+    if m:
+        return "%s_%s" % (_OPS[m.group(1)], t)
+    if "axpy_vec_kernel" in name and "true, true" in name:
+        return "axpy_" + t
+    if re.search(r"\bhorner_kernel<\w+, true>", name):
+        return "horner_" + t
+    m = re.search(r"reduce_tiles_kernel<\w+, (\d)>", name)
+    if m and m.group(1) in ("1", "2"):
+        return ("sum_" if m.group(1) == "1" else "dot_") + t
+    if re.search(r"plain_vec_kernel<\w+, 99,", name):
+        return "vmem_" + t
+    return None
+
+
+def summarize_profiles(prof_dir: str, command: str):
+    """Write profiles/hot_path_step_n2e28_{kernel_trace,counters}.txt and
+    profiles/traffic.json from a rocprofv3 run of this benchmark: kernel
+    statistics (--kernel-trace --stats) in prof_dir/trace, FETCH_SIZE and
+    WRITE_SIZE (--pmc, one counter per run) in prof_dir/fetch and
+    prof_dir/write.  FETCH_SIZE / WRITE_SIZE are scaled by the factor that
+    makes them equal the known bytes of the copy kernel (vmem)."""
+    import csv
+    import glob
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    stats = glob.glob(os.path.join(prof_dir, "trace", "*kernel_stats.csv"))[0]
+    rows = list(csv.DictReader(open(stats)))
+    lines = ["# rocprofv3 kernel statistics of the benchmark step (n = 2^28 elementwise, 2^26 reductions)",
+             "# command: " + command, "# source hash: " + kernel_source_hash(),
+             "%-14s %6s %12s  %s" % ("bench_key", "calls", "avg_us", "kernel")]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        k = bench_key(r["Name"]) or "-"
+        lines.append("%-14s %6s %12.2f  %s" % (k, r["Calls"], float(r["AverageNs"]) / 1e3, r["Name"][:110]))
+    open(os.path.join(out_dir, "hot_path_step_n2e28_kernel_trace.txt"), "w").write("\n".join(lines) + "\n")
+
+    def counters(which):
+        f = glob.glob(os.path.join(prof_dir, which, "*counter_collection.csv"))[0]
+        acc = {}
+        for r in csv.DictReader(open(f)):
+            k = bench_key(r["Kernel_Name"])
+            if k:
+                acc.setdefault(k, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = counters("fetch"), counters("write")
+    traffic = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
+    factors = {}
+    for t, es in (("f64", 8), ("f32", 4)):
+        n = N_STREAM
+        f = (2 * n * es) / (fetch["vmem_" + t] * 1024)
+        w = (n * es) / (write["vmem_" + t] * 1024)
+        factors[t] = (f, w)
+    traffic["scale"] = {t: {"fetch": round(f, 4), "write": round(w, 4)} for t, (f, w) in factors.items()}
+    lines = ["# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per",
+             "# dispatch, one counter per run), scaled so the copy kernel reads and writes its known bytes",
+             "# command: " + command, "# source hash: " + kernel_source_hash(),
+             "# scale factors (fetch, write): " + json.dumps(traffic["scale"]),
+             "%-12s %14s %14s %16s %16s %8s" % ("bench_key", "FETCH_KiB", "WRITE_KiB", "traffic_B",
+                                                "algorithmic_B", "ratio")]
+    for k in sorted(set(fetch) & set(write)):
+        base, t = k.rsplit("_", 1)
+        es = 8 if t == "f64" else 4
+        f, w = factors[t]
+        b = fetch[k] * 1024 * f + write[k] * 1024 * w
+        n = N_REDUCE if base in ("sum", "dot") else N_STREAM
+        words = 3 if base == "vmem" else KERNELS[base][0]
+        alg = words * es * n
+        traffic["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(b),
+                                 "algorithmic_bytes": alg}
+        lines.append("%-12s %14.0f %14.0f %16.0f %16d %8.4f" % (k, fetch[k], write[k], b, alg, b / alg))
+    open(os.path.join(out_dir, "hot_path_step_n2e28_counters.txt"), "w").write("\n".join(lines) + "\n")
+    json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=20000,
+                    help="jobs in the serving stream (0 skips it)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 output in DIR and exit")
+    ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.profile_command)
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: the twofold hot path runs on a single MI355X here; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -323,6 +517,11 @@ def main():
         "kernels": kernels,
         "kernel_source_hash": src_hash,
     }
+    if args.serve_jobs > 0:
+        # the timed passes' buffers are no longer needed
+        del inputs, tcalls, pcalls
+        torch.cuda.empty_cache()
+        result["serving"] = serving_run(torch, W, jobs=args.serve_jobs)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(W)

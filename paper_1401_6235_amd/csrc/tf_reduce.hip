@@ -13,6 +13,9 @@
 //     thread 0 joins the (at most 4) wave results;
 //   * the per-block partials are joined by the same pairing in one more
 //     pass (a second pass only when there are more than 16384 of them).
+//   * within a block, lane t of a wave keeps the wave's t-th subtree value
+//     and a butterfly finishes the wave's aligned group: every tree level
+//     stays in registers.
 #include "tf_tree.hpp"
 
 namespace tf {
@@ -39,15 +42,17 @@ __global__ __launch_bounds__(kBlock) void reduce_tiles_kernel(int64_t n, int64_t
 
 // Partials -> partials of the next level (see block_join).
 template <typename T, bool PLAIN>
-__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int64_t count, int group, int active,
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int64_t count, int64_t span,
                                                                  const Pair<T> *in, Pair<T> *partial,
                                                                  T *out) {
-    const Pair<T> r = block_join<T, PLAIN>(blockIdx.x, count, group, active, in);
+    const Pair<T> r = block_join<T, PLAIN>(blockIdx.x, count, span, in);
     if (threadIdx.x == 0) {
         if (out) write_out(out, r, PLAIN);
         else partial[blockIdx.x] = r;
     }
 }
+
+constexpr int64_t kMaxSpan = 4 * 64 * 64;  // partials one block joins
 
 static int64_t pow2_ceil(int64_t v) {
     int64_t p = 1;
@@ -73,7 +78,7 @@ static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, 
     constexpr bool PLAIN = LeafTraits<LEAF>::plain;
     if (n == 0) {  // empty: the partial pass over zero partials writes (+0, +0)
         hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3(1), dim3(kBlock), 0, L.stream,
-                           (int64_t)0, 1, 1, (const Pair<T> *)nullptr, (Pair<T> *)nullptr, out);
+                           (int64_t)0, (int64_t)1, (const Pair<T> *)nullptr, (Pair<T> *)nullptr, out);
         return;
     }
     const RedShape s = reduce_shape(n);
@@ -84,18 +89,13 @@ static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, 
     int64_t count = s.blocks, padded = s.padded;
     Pair<T> *src = work;
     while (padded > 1) {
-        int64_t group = padded / kBlock;
-        if (group < 1) group = 1;
-        if (group > 64) group = 64;
-        int64_t active = padded / group;
-        if (active > kBlock) active = kBlock;
-        const int64_t span = group * active;
+        const int64_t span = padded < kMaxSpan ? padded : kMaxSpan;
         const int64_t next_padded = padded / span;
         const int64_t next_count = (count + span - 1) / span;
         Pair<T> *dst = src + count;
         const bool last = next_padded == 1;
         hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
-                           L.stream, count, (int)group, (int)active, (const Pair<T> *)src, dst,
+                           L.stream, count, span, (const Pair<T> *)src, dst,
                            last ? out : (T *)nullptr);
         src = dst;
         count = next_count;

@@ -288,10 +288,7 @@ template <typename T>
 __device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
     tfs_done out = {};
     if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
-        const int padded = d.padded;
-        const int group = padded > kBlock ? padded / kBlock : 1;
-        const int active = padded / group;
-        const Pair<T> r = block_join<T, false>(0, d.nclaims, group, active, (const Pair<T> *)d.part);
+        const Pair<T> r = block_join<T, false>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
         const double z0 = (double)r.hi, z1 = (double)r.lo;
         out.z0 = z0;
         out.z1 = z1;

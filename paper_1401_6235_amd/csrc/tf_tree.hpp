@@ -112,101 +112,100 @@ __device__ __forceinline__ Pair<T> level1(const T a0[], const T a1[], const T b0
                                    leaf<T, LEAF>(a0[i + 1], a1[i + 1], b0[i + 1], b1[i + 1]));
 }
 
-// Value of one 256-leaf tile, identical in every lane of the wave.
+// The leaves of one tile held by this lane: binary32 and dotted binary64
+// sums hold 4 consecutive leaves (4l .. 4l+3); other binary64 tiles hold
+// leaves 2l, 2l+1 of each half of the tile (entries 0, 1 and 2, 3), so each
+// 16-byte load instruction is contiguous over the wave.
+template <typename T>
+struct TileData {
+    T a0[4], a1[4], b0[4], b1[4];
+};
+
 template <typename T, int LEAF>
-__device__ __forceinline__ Pair<T> tile_value(int64_t tile, int64_t n, bool aligned, const T *x0,
-                                              const T *x1, const T *y0, const T *y1) {
+constexpr bool halves_layout() {
+    return sizeof(T) == 8 && TF_RED_HALVES && LEAF != LEAF_SUM_D;
+}
+
+template <typename T, int LEAF>
+__device__ __forceinline__ void tile_load(TileData<T> &D, int64_t tile, int64_t n, bool aligned,
+                                          const T *x0, const T *x1, const T *y0, const T *y1) {
     using Tr = LeafTraits<LEAF>;
     const int lane = threadIdx.x & 63;
     const bool vec = aligned && (tile + 1) * kTile <= n;
-    if constexpr (sizeof(T) == 8 && TF_RED_HALVES && LEAF != LEAF_SUM_D) {
-        // binary64, each 16-byte load instruction contiguous over the wave:
-        // lane l holds leaves 2l, 2l+1 of each half of the tile; level 1 in
-        // registers, levels 2-7 by one butterfly per half, level 8 joins
-        // the halves.
-        Pair<T> h[2];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int64_t first = tile * kTile + 128 * k + 2 * lane;
-            T a0[2], a1[2] = {}, b0[2] = {}, b1[2] = {};
-            load2(x0, first, n, vec, a0);
-            if constexpr (Tr::has_x1) load2(x1, first, n, vec, a1);
-            if constexpr (Tr::has_y0) load2(y0, first, n, vec, b0);
-            if constexpr (Tr::has_y1) load2(y1, first, n, vec, b1);
-            h[k] = level1<T, LEAF>(a0, a1, b0, b1, 0);
+    for (int k = 0; k < 4; ++k) D.a1[k] = D.b0[k] = D.b1[k] = T(0);
+    if constexpr (halves_layout<T, LEAF>()) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t first = tile * kTile + 128 * h + 2 * lane;
+            load2(x0, first, n, vec, D.a0 + 2 * h);
+            if constexpr (Tr::has_x1) load2(x1, first, n, vec, D.a1 + 2 * h);
+            if constexpr (Tr::has_y0) load2(y0, first, n, vec, D.b0 + 2 * h);
+            if constexpr (Tr::has_y1) load2(y1, first, n, vec, D.b1 + 2 * h);
         }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) h[k] = butterfly<T, Tr::plain>(h[k], lane);
-        return node<T, Tr::plain>(h[0], h[1]);
     } else {
         const int64_t first = tile * kTile + 4 * lane;
-        T a0[4], a1[4] = {}, b0[4] = {}, b1[4] = {};
-        load4(x0, first, n, vec, a0);
-        if constexpr (Tr::has_x1) load4(x1, first, n, vec, a1);
-        if constexpr (Tr::has_y0) load4(y0, first, n, vec, b0);
-        if constexpr (Tr::has_y1) load4(y1, first, n, vec, b1);
-        const Pair<T> m0 = level1<T, LEAF>(a0, a1, b0, b1, 0);
-        const Pair<T> m1 = level1<T, LEAF>(a0, a1, b0, b1, 2);
+        load4(x0, first, n, vec, D.a0);
+        if constexpr (Tr::has_x1) load4(x1, first, n, vec, D.a1);
+        if constexpr (Tr::has_y0) load4(y0, first, n, vec, D.b0);
+        if constexpr (Tr::has_y1) load4(y1, first, n, vec, D.b1);
+    }
+}
+
+// Tree value of a loaded tile, identical in every lane of the wave.
+template <typename T, int LEAF>
+__device__ __forceinline__ Pair<T> tile_reduce(const TileData<T> &D) {
+    using Tr = LeafTraits<LEAF>;
+    const int lane = threadIdx.x & 63;
+    if constexpr (halves_layout<T, LEAF>()) {
+        // level 1 in registers, levels 2-7 by one butterfly per half (the two
+        // are independent and interleave), level 8 joins the halves
+        Pair<T> h0 = level1<T, LEAF>(D.a0, D.a1, D.b0, D.b1, 0);
+        Pair<T> h1 = level1<T, LEAF>(D.a0, D.a1, D.b0, D.b1, 2);
+        h0 = butterfly<T, Tr::plain>(h0, lane);
+        h1 = butterfly<T, Tr::plain>(h1, lane);
+        return node<T, Tr::plain>(h0, h1);
+    } else {
+        const Pair<T> m0 = level1<T, LEAF>(D.a0, D.a1, D.b0, D.b1, 0);
+        const Pair<T> m1 = level1<T, LEAF>(D.a0, D.a1, D.b0, D.b1, 2);
         return butterfly<T, Tr::plain>(node<T, Tr::plain>(m0, m1), lane);
     }
 }
 
-// Binary counter over consecutive subtree values: after the values of an
-// aligned power-of-two group have been pushed in index order, slot[log2 m]
-// holds their pairwise-tree value.  Uniform control flow.
-template <typename T, bool PLAIN, int SLOTS>
-struct Counter {
-    Pair<T> slot[SLOTS];
-    __device__ __forceinline__ void push(int64_t t, Pair<T> v) {
-        bool placed = false;
-#pragma unroll
-        for (int k = 0; k < SLOTS; ++k) {
-            if (!placed) {
-                if ((t >> k) & 1) {
-                    v = node<T, PLAIN>(slot[k], v);
-                } else {
-                    slot[k] = v;
-                    placed = true;
-                }
-            }
-        }
-    }
-    __device__ __forceinline__ Pair<T> result(int log2m) const {
-        Pair<T> r = slot[0];
-#pragma unroll
-        for (int k = 1; k < SLOTS; ++k)
-            if (log2m == k) r = slot[k];
-        return r;
-    }
-};
+// Value of one 256-leaf tile, identical in every lane of the wave.
+template <typename T, int LEAF>
+__device__ __forceinline__ Pair<T> tile_value(int64_t tile, int64_t n, bool aligned, const T *x0,
+                                              const T *x1, const T *y0, const T *y1) {
+    TileData<T> D;
+    tile_load<T, LEAF>(D, tile, n, aligned, x0, x1, y0, y1);
+    return tile_reduce<T, LEAF>(D);
+}
 
 __device__ __forceinline__ int ilog2(int64_t v) { return 63 - __clzll(v); }
 
-// Value of the aligned subtree of `per_block` tiles (a power of two) that
-// starts at tile b * per_block, computed by one block of 4 waves; valid in
-// thread 0.  Each wave folds per_block / 4 consecutive tiles (or one) with a
-// binary counter and thread 0 joins the wave results.  Tiles at or beyond
-// `tiles` are (+0, +0).  Contains __syncthreads: call from every thread.
-template <typename T, int LEAF>
-__device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64_t n, int64_t tiles,
-                                                 bool aligned, const T *x0, const T *x1, const T *y0,
-                                                 const T *y1) {
-    constexpr bool PLAIN = LeafTraits<LEAF>::plain;
+// Butterfly over the first m lanes (m a power of two, at most 64): the
+// adjacent-pairing tree of the values held by lanes 0 .. m-1, left in each of
+// them.  Lanes at or beyond m pair among themselves and are not used.
+template <typename T, bool PLAIN>
+__device__ __forceinline__ Pair<T> butterfly_m(Pair<T> v, int lane, int m) {
+    for (int d = 1; d < m; d <<= 1) {
+        Pair<T> o;
+        o.hi = __shfl_xor(v.hi, d);
+        o.lo = PLAIN ? T(0) : __shfl_xor(v.lo, d);
+        const bool left = (lane & d) == 0;
+        const Pair<T> l{left ? v.hi : o.hi, left ? v.lo : o.lo};
+        const Pair<T> r{left ? o.hi : v.hi, left ? o.lo : v.lo};
+        v = node<T, PLAIN>(l, r);
+    }
+    return v;
+}
+
+// Join of the (at most 4) wave results of a block, in thread 0.
+template <typename T, bool PLAIN>
+__device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
     __shared__ Pair<T> wres[4];
     const int wave = threadIdx.x >> 6;
-    const int per_wave = per_block >= 4 ? per_block / 4 : 1;
-    const int waves = per_block / per_wave;
-    if (wave < waves) {
-        const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
-        Counter<T, PLAIN, 5> acc;
-        for (int t = 0; t < per_wave; ++t) {
-            const int64_t tile = t0 + t;
-            const Pair<T> v = tile < tiles ? tile_value<T, LEAF>(tile, n, aligned, x0, x1, y0, y1)
-                                           : Pair<T>{T(0), T(0)};
-            acc.push(t, v);
-        }
-        if ((threadIdx.x & 63) == 0) wres[wave] = acc.result(ilog2(per_wave));
-    }
+    if (wave < waves && (threadIdx.x & 63) == 0) wres[wave] = mine;
     __syncthreads();
     Pair<T> r = wres[0];
     if (waves == 2) r = node<T, PLAIN>(wres[0], wres[1]);
@@ -215,38 +214,67 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
     return r;
 }
 
-// Join of the aligned group of group * active partials (powers of two)
-// starting at b * group * active: each of the first `active` threads folds
-// `group` consecutive partials with a binary counter, then the block pairs
-// the thread results level by level.  Partials at index >= count are
-// (+0, +0).  Valid in thread 0; call from every thread.
-template <typename T, bool PLAIN>
-__device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int group, int active,
-                                              const Pair<T> *in) {
-    __shared__ Pair<T> s[kBlock];
-    const int t = threadIdx.x;
-    Pair<T> v{T(0), T(0)};
-    if (t < active) {
-        const int64_t first = (b * active + t) * group;
-        Counter<T, PLAIN, 7> acc;
-        for (int k = 0; k < group; ++k) {
-            const int64_t i = first + k;
-            acc.push(k, i < count ? in[i] : Pair<T>{T(0), T(0)});
+// Value of the aligned subtree of `per_block` tiles (a power of two, at most
+// 64 * 4) that starts at tile b * per_block, computed by one block of 4
+// waves; valid in thread 0.  Each wave takes per_block / 4 consecutive tiles
+// (or one); lane t keeps the value of the wave's tile t, and a butterfly over
+// those lanes gives the wave's subtree.  Tiles at or beyond `tiles` are
+// (+0, +0).  Contains __syncthreads: call from every thread.
+template <typename T, int LEAF>
+__device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64_t n, int64_t tiles,
+                                                 bool aligned, const T *x0, const T *x1, const T *y0,
+                                                 const T *y1) {
+    constexpr bool PLAIN = LeafTraits<LEAF>::plain;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int per_wave = per_block >= 4 ? per_block / 4 : 1;
+    const int waves = per_block / per_wave;
+    Pair<T> mine{T(0), T(0)};
+    if (wave < waves) {
+        const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
+        // software pipeline: the next tile's loads are in flight while the
+        // current tile is reduced
+        TileData<T> cur, nxt;
+        if (t0 < tiles) tile_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
+        for (int t = 0; t < per_wave; ++t) {
+            const int64_t tile = t0 + t;
+            if (t + 1 < per_wave && tile + 1 < tiles)
+                tile_load<T, LEAF>(nxt, tile + 1, n, aligned, x0, x1, y0, y1);
+            if (tile < tiles) {
+                const Pair<T> v = tile_reduce<T, LEAF>(cur);
+                if (lane == t) mine = v;
+            }
+            cur = nxt;
         }
-        v = acc.result(ilog2(group));
+        mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
     }
-    s[t] = v;
-    __syncthreads();
-    for (int w = active; w > 1; w >>= 1) {
-        Pair<T> r{T(0), T(0)};
-        if (t < w / 2) r = node<T, PLAIN>(s[2 * t], s[2 * t + 1]);
-        __syncthreads();
-        if (t < w / 2) s[t] = r;
-        __syncthreads();
+    return join_waves<T, PLAIN>(mine, waves);
+}
+
+// Join of the aligned group of `span` partials (a power of two, at most
+// 4 * 64 * 64) starting at b * span; partials at index >= count are
+// (+0, +0).  Each wave folds span / 4 consecutive partials (or one) in
+// chunks of 64 lanes, lane j keeping chunk j; valid in thread 0.  Call from
+// every thread.
+template <typename T, bool PLAIN>
+__device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t span, const Pair<T> *in) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t per_wave = span >= 4 ? span / 4 : 1;
+    const int waves = (int)(span / per_wave);
+    Pair<T> mine{T(0), T(0)};
+    if (wave < waves) {
+        const int64_t first = b * span + (int64_t)wave * per_wave;
+        const int64_t width = per_wave < 64 ? per_wave : 64;
+        const int64_t chunks = per_wave / width;
+        for (int64_t j = 0; j < chunks; ++j) {
+            const int64_t i = first + j * width + lane;
+            Pair<T> v = (lane < width && i < count) ? in[i] : Pair<T>{T(0), T(0)};
+            v = butterfly_m<T, PLAIN>(v, lane, (int)width);
+            if (lane == j) mine = v;
+            if (chunks == 1) mine = v;
+        }
+        mine = butterfly_m<T, PLAIN>(mine, lane, (int)chunks);
     }
-    const Pair<T> r = s[0];
-    __syncthreads();
-    return r;
+    return join_waves<T, PLAIN>(mine, waves);
 }
 
 }  // namespace tf
