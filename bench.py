@@ -260,23 +260,9 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
     descs = [job_of(j) for j in sched]
     torch.cuda.synchronize()
     srv = S.Server(0, budget, S.TFS_MAX_SLOTS)
-    results = {}
     try:
         log("serving: %d jobs at %.0f jobs/s" % (jobs, rate))
-        t0 = S.tfs_clock() + 0.05
-        ids = []
-        for j, desc in zip(sched, descs):
-            ta = t0 + j["t"]
-            while S.tfs_clock() < ta:
-                pass
-            ids.append(srv.submit(desc, t_arrive=ta))
-            for r in srv.poll():
-                results[r["id"]] = r
-        deadline = time.time() + 120
-        while len(results) < jobs and time.time() < deadline:
-            for r in srv.poll():
-                results[r["id"]] = r
-            time.sleep(0.001)
+        ids, results = S.run_stream(srv, [j["t"] for j in sched], descs)
         stats = srv.stats()
     finally:
         srv.close()

@@ -139,3 +139,26 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def run_stream(srv: "Server", times, jobs, keep=None, t0_delay: float = 0.05, timeout: float = 120.0):
+    """Submit jobs[k] at tfs_clock() time t0 + times[k] (busy-waiting on the
+    clock, polling completions in between) and wait for all results.
+    Returns (ids, {id: result}); arrival times are the scheduled ones, so
+    any lateness of this driver counts against the measured latency."""
+    import time as _time
+    t0 = tfs_clock() + t0_delay
+    ids, results = [], {}
+    for k, (t, job) in enumerate(zip(times, jobs)):
+        ta = t0 + t
+        while tfs_clock() < ta:
+            pass
+        ids.append(srv.submit(job, t_arrive=ta, keep=None if keep is None else keep[k]))
+        for r in srv.poll():
+            results[r["id"]] = r
+    deadline = _time.time() + timeout
+    while len(results) < len(ids) and _time.time() < deadline:
+        for r in srv.poll():
+            results[r["id"]] = r
+        _time.sleep(0.001)
+    return ids, results

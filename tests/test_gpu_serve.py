@@ -213,15 +213,10 @@ def test_poisson_stream_agrees_with_oracle():
     srv = S.Server(0, 8 << 30, 64)
     try:
         step("serve poisson stream 1000 jobs")
-        t0 = S.tfs_clock()
-        ids = []
-        for j in sched:
-            while S.tfs_clock() - t0 < j["t"]:
-                pass
-            ids.append(srv.submit(make(j), t_arrive=t0 + j["t"]))
-        got = wait_all(srv, len(sched))
+        ids, got = S.run_stream(srv, [j["t"] for j in sched], [make(j) for j in sched])
     finally:
         srv.close()
+    assert len(got) == len(sched)
     lat = np.array([got[i]["t_done"] - got[i]["t_arrive"] for i in ids])
     step("p50 %.1f us p99 %.1f us" % (np.percentile(lat, 50) * 1e6, np.percentile(lat, 99) * 1e6))
     flags = 0
@@ -229,6 +224,52 @@ def test_poisson_stream_agrees_with_oracle():
         check(got[i], expected(j), "stream")
         flags += got[i]["flag"]
     assert flags >= 1
+
+
+def test_full_stream_sampled_against_oracle():
+    """The full serving configuration (20,000 jobs at 2,000 jobs/s, lengths
+    2^8 .. 2^24, 5 % ill-conditioned, 64 GiB budget): every job completes
+    with status OK, every ill-conditioned job is flagged, and 200 sampled
+    jobs (plus every ill-conditioned sum / dot) equal the oracle exactly."""
+    torch = torch_cuda()
+    sched = W.serve_schedule(20000, 2000.0, seed=1)
+    inst = {}
+    for j in sched:
+        if j["illcond"] and j["op"] in ("sum", "dot"):
+            n2 = min(max(1 << int(round(np.log2(j["n"]))), 256), 1 << 24)
+            j["n"] = n2
+            if (n2, j["dtype"]) not in inst:
+                d = W.illdot_case(n2, 1e20, seed=n2, dtype=NP[j["dtype"]])
+                hi, lo = W.product_split(d["x"], d["y"])
+                inst[(n2, j["dtype"])] = {"x": d["x"], "y": d["y"], "hi": hi, "lo": lo}
+    gpu = {k: {a: to_gpu(b) for a, b in v.items()} for k, v in inst.items()}
+    for j in sched:
+        if j["illcond"] and j["op"] in ("sum", "dot"):
+            h, g = inst[(j["n"], j["dtype"])], gpu[(j["n"], j["dtype"])]
+            if j["op"] == "dot":
+                j["provided"], j["provided_gpu"] = {"x0": h["x"], "y0": h["y"]}, {"x0": g["x"], "y0": g["y"]}
+            else:
+                j["provided"], j["provided_gpu"] = {"x0": h["hi"], "x1": h["lo"]}, {"x0": g["hi"], "x1": g["lo"]}
+    descs = [make(j) for j in sched]
+    srv = S.Server(0, 64 << 30, 64)
+    try:
+        step("serve full stream 20000 jobs")
+        ids, got = S.run_stream(srv, [j["t"] for j in sched], descs)
+    finally:
+        srv.close()
+    assert len(got) == len(sched)
+    assert all(r["status"] == 0 for r in got.values())
+    for j, i in zip(sched, ids):
+        if j["illcond"]:
+            assert got[i]["flag"] == 1, j
+    rng = np.random.default_rng(0)
+    sample = set(rng.choice(len(sched), 200, replace=False).tolist())
+    sample |= {k for k, j in enumerate(sched) if j.get("provided") is not None}
+    step("checking %d sampled jobs against the oracle" % len(sample))
+    for k in sorted(sample):
+        check(got[ids[k]], expected(sched[k]), "full stream #%d" % k)
+    del gpu
+    torch.cuda.empty_cache()
 
 
 def test_tight_budget_forces_waits():
