@@ -286,8 +286,18 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
         else:
             agree["random"] += 1
             agree["random_flagged"] += r["flag"]
+    def p50(xs):
+        return round(float(np.percentile(np.array(xs), 50)) * 1e6, 1)
+
+    breakdown = {
+        "driver_late_us_p50": p50([r["t_submit"] - r["t_arrive"] for r in res]),
+        "admit_us_p50": p50([r["t_admit"] - r["t_submit"] for r in res]),
+        "materialise_publish_us_p50": p50([r["t_publish"] - r["t_admit"] for r in res]),
+        "device_and_completion_us_p50": p50([r["t_done"] - r["t_publish"] for r in res]),
+    }
     return {
         "jobs": jobs, "completed": len(res), "rate_offered": rate,
+        "latency_breakdown": breakdown,
         "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
         "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
         "mean_us": round(float(lat.mean()) * 1e6, 1),

@@ -256,7 +256,9 @@ typedef struct {
     uint64_t n_flagged;            /* axpy / Horner: elements over threshold */
     uint64_t nonfinite;            /* non-finite results */
     uint64_t hash_z0, hash_z1;     /* axpy / Horner: sum of bit patterns mod 2^64 */
-    double t_arrive, t_admit, t_publish, t_done; /* seconds, tfs_clock() */
+    double t_arrive;  /* scheduled arrival (tfs_submit argument), tfs_clock() seconds */
+    double t_submit;  /* when tfs_submit was called */
+    double t_admit, t_publish, t_done; /* admitted, published to the device, completion seen */
     double device_us;              /* first claim to completion on the device */
 } tfs_result;
 
@@ -288,8 +290,9 @@ int tfs_get_stats(tfs_server *s, tfs_stats *out);
 /* Seconds on the server clock (monotonic, process-wide). */
 double tfs_clock(void);
 
-/* Stop the persistent kernel (jobs in flight finish first is not waited
- * for: pending jobs are dropped), free everything. */
+/* Stop the server: jobs already published to the device run to
+ * completion before the persistent kernel exits, queued jobs are dropped;
+ * then free everything. */
 int tfs_destroy(tfs_server *s);
 
 #ifdef __cplusplus

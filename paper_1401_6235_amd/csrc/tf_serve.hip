@@ -4,11 +4,12 @@
 // host-coherent descriptor ring (system-scope acquire), copies each new
 // descriptor into its device slot and opens the slot with a release store of
 // the slot's control word.  Every other block is a worker: its first wave
-// reads the 64 control words (one per lane), picks the oldest job with an
-// unclaimed unit and claims it with a compare-and-swap on the control word
-// (the generation in the word makes a stale claim fail); the whole block
-// processes the unit (a 16384-leaf aligned subtree of a sum / dot, or 16384
-// elements of an axpy / Horner), then bumps the job's done counter.  The
+// reads the 64 control words (one per lane), picks the job with the fewest
+// unclaimed units (oldest first among equals) and claims its next unit with
+// a compare-and-swap on the control word (the generation in the word makes a
+// stale claim fail); the whole block processes the unit (a 4096-leaf
+// aligned subtree of a sum / dot, or 4096 elements of an axpy / Horner),
+// then bumps the job's done counter.  The
 // block that completes a job's last unit joins the per-unit partials and
 // writes the job's completion record (generation last, system-scope
 // release).  Workers never wait for each other, so the grid needs no
@@ -149,16 +150,23 @@ __device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
         while (consumed < pub) {
             // plain loads after the acquire above: independent, so they
             // pipeline over the host link instead of one round trip each
-            const tfs_desc tmp = sh->ring[consumed % TFS_RING];
+            const tfs_desc *e = &sh->ring[consumed % TFS_RING];
+            const int slot = e->slot;
+            const uint64_t gen = e->gen;
+            const int nclaims = e->nclaims;
             ++consumed;
+            if (slot >= 0 && slot < TFS_MAX_SLOTS) {  // a malformed entry is skipped
+                DevSlot *s = &st->slot[slot];
+                const uint64_t *src = (const uint64_t *)e;
+                uint64_t *dst = (uint64_t *)&s->d;
+#pragma unroll
+                for (unsigned k = 0; k < sizeof(tfs_desc) / 8; ++k) dst[k] = src[k];
+                s->done = 0;
+                s->t_start = 0;
+                __hip_atomic_store(&s->ctl, TFS_CTL(gen, nclaims, 0), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
             st_rel_sys(&sh->consumed, consumed);
-            if (tmp.slot < 0 || tmp.slot >= TFS_MAX_SLOTS) continue;  // malformed entry: skip
-            DevSlot *s = &st->slot[tmp.slot];
-            s->d = tmp;
-            s->done = 0;
-            s->t_start = 0;
-            __hip_atomic_store(&s->ctl, TFS_CTL(tmp.gen, tmp.nclaims, 0), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
         }
         if (fresh) last = wall_clock64();
         if (ld_acq_sys(&sh->stop)) break;
@@ -233,27 +241,83 @@ __device__ __forceinline__ void account(tfs_vsum &acc, T z0, T z1, double thr) {
 
 // ---- one unit of an axpy / Horner job ----------------------------------------
 
+// Horner element with the coefficients read from the block's copy of the
+// descriptor (already rounded to T), the same steps as horner_one.
+template <typename T, bool XT>
+__device__ __forceinline__ Pair<T> horner_desc(const double *c, int degree, T x0, T x1) {
+    Pair<T> r{(T)c[degree], T(0)};
+    for (int k = degree - 1; k >= 0; --k) {
+        const Pair<T> m = XT ? mul_tt(r.hi, r.lo, x0, x1) : mul_td(r.hi, r.lo, x0);
+        r = add_td(m.hi, m.lo, (T)c[k]);
+    }
+    return r;
+}
+
+template <typename T, int OP, bool XT, bool YT>
+__device__ __forceinline__ Pair<T> vector_elem(const tfs_desc &d, T a0, T a1, T x0, T x1, T y0, T y1) {
+    if constexpr (OP == TFS_OP_AXPY) return axpy_one<T, XT, YT>(a0, a1, x0, x1, y0, y1);
+    else return horner_desc<T, XT>(d.c, d.degree, x0, x1);
+}
+
+// TFS_CLAIM elements: 16 per thread as 16-byte vectors, four vectors per
+// operand in flight, consecutive threads on consecutive vectors; a short
+// or misaligned unit takes a scalar loop.
 template <typename T, int OP, bool XT, bool YT>
 __device__ void claim_vector(const tfs_desc &d, int claim) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::N;
+    constexpr int NV = TFS_CLAIM / kBlock / W;  // vectors per thread
+    constexpr int U = NV < 4 ? NV : 4;
+    constexpr bool HAS_Y = OP == TFS_OP_AXPY;
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
     T *z0 = (T *)d.z0, *z1 = (T *)d.z1;
+    const int t = threadIdx.x;
     const int64_t base = (int64_t)claim * TFS_CLAIM;
     const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
-    tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
-    Coeffs<T> C;
-    if constexpr (OP == TFS_OP_HORNER)
-        for (int k = 0; k <= d.degree; ++k) C.c[k] = (T)d.c[k];
+    const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1 | d.z0 | d.z1) & 15u) == 0;
     const T a0 = (T)d.a0, a1 = (T)d.a1;
-    for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
-        Pair<T> z;
-        if constexpr (OP == TFS_OP_AXPY) z = axpy_one<T, XT, YT>(a0, a1, x0[i], XT ? x1[i] : T(0), y0[i], YT ? y1[i] : T(0));
-        else z = horner_one<T, XT>(C, d.degree, x0[i], XT ? x1[i] : T(0));
-        z0[i] = z.hi;
-        z1[i] = z.lo;
-        account(acc, z.hi, z.lo, d.thr);
+    tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
+    if (aligned && end == base + TFS_CLAIM) {
+        const int64_t vb = base / W;
+#pragma unroll
+        for (int j0 = 0; j0 < NV; j0 += U) {
+            V p0[U], p1[U], q0[U], q1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = vb + (int64_t)(j0 + u) * kBlock + t;
+                p0[u] = vload(x0, i);
+                if constexpr (XT) p1[u] = vload(x1, i);
+                if constexpr (HAS_Y) q0[u] = vload(y0, i);
+                if constexpr (HAS_Y && YT) q1[u] = vload(y1, i);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                V r0, r1;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const Pair<T> z = vector_elem<T, OP, XT, YT>(d, a0, a1, p0[u][k], XT ? p1[u][k] : T(0),
+                                                                HAS_Y ? q0[u][k] : T(0),
+                                                                (HAS_Y && YT) ? q1[u][k] : T(0));
+                    r0[k] = z.hi;
+                    r1[k] = z.lo;
+                    account(acc, z.hi, z.lo, d.thr);
+                }
+                const int64_t i = vb + (int64_t)(j0 + u) * kBlock + t;
+                vstore(z0, i, r0);
+                vstore(z1, i, r1);
+            }
+        }
+    } else {
+        for (int64_t i = base + t; i < end; i += kBlock) {
+            const Pair<T> z = vector_elem<T, OP, XT, YT>(d, a0, a1, x0[i], XT ? x1[i] : T(0),
+                                                        HAS_Y ? y0[i] : T(0), (HAS_Y && YT) ? y1[i] : T(0));
+            z0[i] = z.hi;
+            z1[i] = z.lo;
+            account(acc, z.hi, z.lo, d.thr);
+        }
     }
     const tfs_vsum r = block_summary(acc);
-    if (threadIdx.x == 0) ((tfs_vsum *)d.part)[claim] = r;
+    if (t == 0) ((tfs_vsum *)d.part)[claim] = r;
 }
 
 template <typename T>
@@ -344,8 +408,9 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
     while (true) {
         if (t < 64) {
             const uint64_t c = __hip_atomic_load(&st->slot[t].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t gen = TFS_CTL_GEN(c);
-            const uint64_t key = (gen != 0 && TFS_CTL_NEXT(c) < TFS_CTL_NTILES(c)) ? gen : ~0ull;
+            const uint64_t gen = TFS_CTL_GEN(c), nt = TFS_CTL_NTILES(c), nx = TFS_CTL_NEXT(c);
+            // shortest remaining job first (fewest unclaimed units), then oldest
+            const uint64_t key = (gen != 0 && nx < nt) ? ((nt - nx) << 36) | gen : ~0ull;
             uint64_t m = key;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
@@ -357,7 +422,7 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                     const bool stop = __hip_atomic_load(&st->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0;
                     s_slot = stop ? -3 : -1;
                 }
-            } else if (key == m) {  // the one lane holding the oldest open job
+            } else if (key == m) {  // the one lane holding the chosen job
                 uint64_t expected = c;
                 const bool ok = __hip_atomic_compare_exchange_strong(
                     &st->slot[t].ctl, &expected, c + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -520,6 +585,7 @@ tfs_server *tfs_create(int device, uint64_t budget_bytes, int max_slots) {
         return nullptr;
     }
     s->server = new tfs::Server(&s->dev, budget_bytes, max_slots);
+    s->server->set_tick_hz(s->dev.tick_hz());
     if (s->server->start() != TF_OK) {
         delete s->server;
         delete s;

@@ -192,24 +192,27 @@ class Server {
         }
     }
 
+    // Client side: queue a job (only the inbox lock is taken, so a client
+    // never waits behind the server thread's device queries).
     int submit(const tfs_job &j, double t_arrive, uint64_t *id) {
         Plan p;
         const int st = plan_job(j, &p);
         if (st != TF_OK) return st;
         if (p.bytes > pool_.capacity()) return TF_ENOMEM;  // can never be admitted
-        std::lock_guard<std::mutex> g(mu_);
         Pending q;
         q.job = j;
         q.plan = p;
+        q.t_submit = now_s();
+        q.t_arrive = t_arrive > 0 ? t_arrive : q.t_submit;
+        std::lock_guard<std::mutex> g(in_mu_);
         q.id = ++next_id_;
-        q.t_arrive = t_arrive > 0 ? t_arrive : now_s();
-        pending_.push_back(q);
+        inbox_.push_back(q);
         if (id) *id = q.id;
         return TF_OK;
     }
 
     int poll(tfs_result *out, int max) {
-        std::lock_guard<std::mutex> g(mu_);
+        std::lock_guard<std::mutex> g(out_mu_);
         int k = 0;
         while (k < max && !completed_.empty()) {
             out[k++] = completed_.front();
@@ -219,18 +222,19 @@ class Server {
     }
 
     void stats(tfs_stats *s) {
-        std::lock_guard<std::mutex> g(mu_);
         memset(s, 0, sizeof *s);
-        s->pending = (int64_t)pending_.size();
-        int inflight = 0;
-        for (int i = 0; i < TFS_MAX_SLOTS; ++i) inflight += slots_[i].busy;
-        s->in_flight = inflight;
-        s->completed = (int64_t)n_completed_;
+        {
+            std::lock_guard<std::mutex> g(in_mu_);
+            s->pending = (int64_t)inbox_.size();
+        }
+        s->pending += pending_count_.load();
+        s->in_flight = in_flight_.load();
+        s->completed = (int64_t)n_completed_.load();
         s->budget_bytes = pool_.capacity();
-        s->resident_bytes = pool_.capacity() - pool_.free_bytes();
-        s->peak_resident_bytes = peak_resident_;
-        s->admission_waits = admission_waits_;
-        s->kernel_alive = dev_->running() ? 1 : 0;
+        s->resident_bytes = resident_.load();
+        s->peak_resident_bytes = peak_resident_.load();
+        s->admission_waits = admission_waits_.load();
+        s->kernel_alive = alive_.load() ? 1 : 0;
     }
 
   private:
@@ -238,7 +242,7 @@ class Server {
         tfs_job job;
         Plan plan;
         uint64_t id;
-        double t_arrive;
+        double t_arrive, t_submit;
     };
     struct Slot {
         bool busy;
@@ -290,7 +294,7 @@ class Server {
         d.part = base + p.off_part;
     }
 
-    // Admit FIFO jobs while a slot and pool space are free.  Called with mu_.
+    // Admit FIFO jobs while a slot and pool space are free (server thread).
     bool admit() {
         bool progress = false;
         while (!pending_.empty()) {
@@ -316,7 +320,9 @@ class Server {
             s.t_admit = now_s();
             fill_desc(s, ++gen_, slot);
             const uint64_t resident = pool_.capacity() - pool_.free_bytes();
+            resident_ = resident;
             if (resident > peak_resident_) peak_resident_ = resident;
+            ++in_flight_;
             if (s.job.job.kind == TFS_KIND_PROVIDED) {
                 s.token = -1;
                 s.stage = 2;
@@ -357,9 +363,11 @@ class Server {
             if (s.stage == 2) {
                 const uint64_t g = __atomic_load_n(&sh->done[i].gen, __ATOMIC_ACQUIRE);
                 if (g == s.desc.gen) {
-                    complete(s, sh->done[i]);
                     pool_.release(s.off, s.job.plan.bytes);
+                    resident_ = pool_.capacity() - pool_.free_bytes();
                     s.busy = false;
+                    --in_flight_;
+                    complete(s, sh->done[i]);
                     progress = true;
                 }
             }
@@ -386,27 +394,41 @@ class Server {
         r.hash_z0 = d.hash0;
         r.hash_z1 = d.hash1;
         r.t_arrive = s.job.t_arrive;
+        r.t_submit = s.job.t_submit;
         r.t_admit = s.t_admit;
         r.t_publish = s.t_publish;
         r.t_done = now_s();
-        r.device_us = d.t_end > d.t_start ? (double)(d.t_end - d.t_start) * 1e6 / 100e6 : 0.0;
-        completed_.push_back(r);
+        r.device_us = d.t_end > d.t_start ? (double)(d.t_end - d.t_start) * 1e6 / tick_hz_ : 0.0;
+        {
+            std::lock_guard<std::mutex> g(out_mu_);
+            completed_.push_back(r);
+        }
         ++n_completed_;
     }
 
+    // Server thread: owns pending_, slots_ and pool_ without locks.
     void loop() {
+        double next_check = 0.0;
         while (running_) {
-            bool progress;
             {
-                std::lock_guard<std::mutex> g(mu_);
-                progress = admit();
-                progress |= progress_slots();
-                progress |= admit();
+                std::lock_guard<std::mutex> g(in_mu_);
+                while (!inbox_.empty()) {
+                    pending_.push_back(inbox_.front());
+                    inbox_.pop_front();
+                }
             }
-            if (!dev_->running() && running_) {
-                dev_->start();  // the worker drained after an idle period: relaunch
+            bool progress = admit();
+            progress |= progress_slots();
+            progress |= admit();
+            pending_count_ = (int64_t)pending_.size();
+            const double t = now_s();
+            if (t >= next_check) {  // liveness of the persistent worker, once a millisecond
+                next_check = t + 1e-3;
+                const bool alive = dev_->running();
+                alive_ = alive;
+                if (!alive && running_) dev_->start();  // drained after an idle period: relaunch
             }
-            if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(10));
+            if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(5));
         }
     }
 
@@ -414,14 +436,20 @@ class Server {
     Pool pool_;
     int max_slots_;
     Slot slots_[TFS_MAX_SLOTS];
-    std::deque<Pending> pending_;
-    std::deque<tfs_result> completed_;
-    std::mutex mu_;
+    std::deque<Pending> inbox_;      // submitted, not yet seen by the server thread (in_mu_)
+    std::deque<Pending> pending_;    // queued for admission (server thread only)
+    std::deque<tfs_result> completed_;  // out_mu_
+    std::mutex in_mu_, out_mu_;
     std::thread thread_;
-    std::atomic<bool> running_{false};
-    uint64_t next_id_ = 0, gen_ = 0, published_ = 0, n_completed_ = 0;
-    uint64_t peak_resident_ = 0, admission_waits_ = 0;
+    std::atomic<bool> running_{false}, alive_{true};
+    uint64_t next_id_ = 0, gen_ = 0, published_ = 0;
+    std::atomic<uint64_t> n_completed_{0}, peak_resident_{0}, admission_waits_{0}, resident_{0};
+    std::atomic<int64_t> pending_count_{0}, in_flight_{0};
     bool head_waited_ = false;
+    double tick_hz_ = 100e6;
+
+  public:
+    void set_tick_hz(double hz) { tick_hz_ = hz; }
 };
 
 }  // namespace tfs

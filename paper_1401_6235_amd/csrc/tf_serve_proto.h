@@ -25,17 +25,17 @@
 #include "tf.h" /* TFS_MAX_SLOTS, TFS_OP_*, TFS_KIND_* */
 
 #define TFS_RING 256           /* descriptor ring entries (power of two) */
-#define TFS_CLAIM 16384        /* elements per claimed unit of work */
-#define TFS_MAX_CLAIMS 4095    /* claims per job (12-bit field) */
+#define TFS_CLAIM 4096         /* elements per claimed unit of work */
+#define TFS_MAX_CLAIMS 16383   /* claims per job (14-bit field) */
 #define TFS_MAX_N ((int64_t)TFS_CLAIM * TFS_MAX_CLAIMS)
 
-/* Control word of a device slot: generation (40 bits), number of claims
- * (12 bits), next unclaimed claim (12 bits).  gen == 0: slot empty. */
+/* Control word of a device slot: generation (36 bits), number of claims
+ * (14 bits), next unclaimed claim (14 bits).  gen == 0: slot empty. */
 #define TFS_CTL(gen, ntiles, next)                                                   \
-    (((uint64_t)(gen) << 24) | ((uint64_t)(ntiles) << 12) | (uint64_t)(next))
-#define TFS_CTL_GEN(c) ((c) >> 24)
-#define TFS_CTL_NTILES(c) (((c) >> 12) & 0xfffu)
-#define TFS_CTL_NEXT(c) ((c)&0xfffu)
+    (((uint64_t)(gen) << 28) | ((uint64_t)(ntiles) << 14) | (uint64_t)(next))
+#define TFS_CTL_GEN(c) ((c) >> 28)
+#define TFS_CTL_NTILES(c) (((c) >> 14) & 0x3fffu)
+#define TFS_CTL_NEXT(c) ((c)&0x3fffu)
 
 typedef struct {
     uint64_t gen;      /* publication number, 1, 2, ... */
