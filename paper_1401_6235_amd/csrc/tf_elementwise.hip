@@ -23,26 +23,38 @@
 #ifndef TF_PLAIN_UNROLL
 #define TF_PLAIN_UNROLL 4
 #endif
+// Threads per block and consecutive block-sized groups of vectors one block
+// walks through (1: one-shot grid).
+#ifndef TF_EW_BLOCK
+#define TF_EW_BLOCK 256
+#endif
+#ifndef TF_EW_CHUNK
+#define TF_EW_CHUNK 1
+#endif
 
 namespace tf {
+
+constexpr int kEwBlock = TF_EW_BLOCK;
 
 // ---------------------------------------------------------------------------
 // twofold binary / unary operations
 // ---------------------------------------------------------------------------
 
 template <typename T, int OP, bool XT, bool YT, int UNROLL>
-__global__ __launch_bounds__(kBlock) void ew_vec_kernel(int64_t n, const T *x0, const T *x1,
+__global__ __launch_bounds__(kEwBlock) void ew_vec_kernel(int64_t n, const T *x0, const T *x1,
                                                         const T *y0, const T *y1, T *z0, T *z1) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     constexpr bool HAS_Y = OP != OP_SQRT;
     const int64_t nvec = n / W;
-    const int64_t step = (int64_t)gridDim.x * kBlock * UNROLL;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock * UNROLL + threadIdx.x; base < nvec; base += step) {
+    for (int64_t grp = (int64_t)blockIdx.x * TF_EW_CHUNK; grp * kEwBlock * UNROLL < nvec;
+         grp += (int64_t)gridDim.x * TF_EW_CHUNK)
+    for (int64_t c = 0, base = grp * kEwBlock * UNROLL + threadIdx.x; c < TF_EW_CHUNK && base < nvec;
+         ++c, base += (int64_t)kEwBlock * UNROLL) {
         V a0[UNROLL], a1[UNROLL], b0[UNROLL], b1[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 a0[u] = vload(x0, i);
                 if constexpr (XT) a1[u] = vload(x1, i);
@@ -52,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void ew_vec_kernel(int64_t n, const T *x0, 
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 V r0, r1;
 #pragma unroll
@@ -100,8 +112,8 @@ static void launch_ew(const Launch &L, int64_t n, const T *x0, const T *x1, cons
                                            : TF_EW_UNROLL_F32;
     if (L.aligned) {
         const int64_t nvec = n / Vec<T>::N;
-        const unsigned g = grid_for(nvec, (int64_t)kBlock * UNROLL, L.cap);
-        hipLaunchKernelGGL((ew_vec_kernel<T, OP, XT, YT, UNROLL>), dim3(g), dim3(kBlock), 0, L.stream,
+        const unsigned g = grid_for(nvec, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
+        hipLaunchKernelGGL((ew_vec_kernel<T, OP, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream,
                            n, x0, x1, y0, y1, z0, z1);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);
@@ -149,17 +161,19 @@ template void run_elementwise<float>(const Launch &, int, int64_t, const void *,
 constexpr int OP_COPY = 99;
 
 template <typename T, int OP, int UNROLL>
-__global__ __launch_bounds__(kBlock) void plain_vec_kernel(int64_t n, const T *x, const T *y, T *z) {
+__global__ __launch_bounds__(kEwBlock) void plain_vec_kernel(int64_t n, const T *x, const T *y, T *z) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     constexpr bool HAS_Y = OP != OP_SQRT;
     const int64_t nvec = n / W;
-    const int64_t step = (int64_t)gridDim.x * kBlock * UNROLL;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock * UNROLL + threadIdx.x; base < nvec; base += step) {
+    for (int64_t grp = (int64_t)blockIdx.x * TF_EW_CHUNK; grp * kEwBlock * UNROLL < nvec;
+         grp += (int64_t)gridDim.x * TF_EW_CHUNK)
+    for (int64_t c = 0, base = grp * kEwBlock * UNROLL + threadIdx.x; c < TF_EW_CHUNK && base < nvec;
+         ++c, base += (int64_t)kEwBlock * UNROLL) {
         V a[UNROLL], b[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 a[u] = vload(x, i);
                 if constexpr (HAS_Y) b[u] = vload(y, i);
@@ -167,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void plain_vec_kernel(int64_t n, const T *x
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 V r;
 #pragma unroll
@@ -207,8 +221,8 @@ template <typename T, int OP>
 static void launch_plain(const Launch &L, int64_t n, const T *x, const T *y, T *z) {
     constexpr int UNROLL = TF_PLAIN_UNROLL;
     if (L.aligned) {
-        const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kBlock * UNROLL, L.cap);
-        hipLaunchKernelGGL((plain_vec_kernel<T, OP, UNROLL>), dim3(g), dim3(kBlock), 0, L.stream, n, x,
+        const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
+        hipLaunchKernelGGL((plain_vec_kernel<T, OP, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n, x,
                            y, z);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);
@@ -237,18 +251,20 @@ template void run_plain<float>(const Launch &, int, int64_t, const void *, const
 // ---------------------------------------------------------------------------
 
 template <typename T, bool XT, bool YT, int UNROLL>
-__global__ __launch_bounds__(kBlock) void axpy_vec_kernel(int64_t n, T a0, T a1, const T *x0,
+__global__ __launch_bounds__(kEwBlock) void axpy_vec_kernel(int64_t n, T a0, T a1, const T *x0,
                                                           const T *x1, const T *y0, const T *y1,
                                                           T *z0, T *z1) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     const int64_t nvec = n / W;
-    const int64_t step = (int64_t)gridDim.x * kBlock * UNROLL;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock * UNROLL + threadIdx.x; base < nvec; base += step) {
+    for (int64_t grp = (int64_t)blockIdx.x * TF_EW_CHUNK; grp * kEwBlock * UNROLL < nvec;
+         grp += (int64_t)gridDim.x * TF_EW_CHUNK)
+    for (int64_t c = 0, base = grp * kEwBlock * UNROLL + threadIdx.x; c < TF_EW_CHUNK && base < nvec;
+         ++c, base += (int64_t)kEwBlock * UNROLL) {
         V p0[UNROLL], p1[UNROLL], q0[UNROLL], q1[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 p0[u] = vload(x0, i);
                 if constexpr (XT) p1[u] = vload(x1, i);
@@ -258,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void axpy_vec_kernel(int64_t n, T a0, T a1,
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t i = base + (int64_t)u * kBlock;
+            const int64_t i = base + (int64_t)u * kEwBlock;
             if (i < nvec) {
                 V r0, r1;
 #pragma unroll
@@ -302,8 +318,8 @@ static void launch_axpy(const Launch &L, int64_t n, T a0, T a1, const T *x0, con
                         const T *y0, const T *y1, T *z0, T *z1) {
     constexpr int UNROLL = sizeof(T) == 8 ? TF_EW_UNROLL_F64 : TF_EW_UNROLL_F32;
     if (L.aligned) {
-        const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kBlock * UNROLL, L.cap);
-        hipLaunchKernelGGL((axpy_vec_kernel<T, XT, YT, UNROLL>), dim3(g), dim3(kBlock), 0, L.stream, n,
+        const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
+        hipLaunchKernelGGL((axpy_vec_kernel<T, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n,
                            a0, a1, x0, x1, y0, y1, z0, z1);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);

@@ -229,8 +229,9 @@ def test_poisson_stream_agrees_with_oracle():
 def test_full_stream_sampled_against_oracle():
     """The full serving configuration (20,000 jobs at 2,000 jobs/s, lengths
     2^8 .. 2^24, 5 % ill-conditioned, 64 GiB budget): every job completes
-    with status OK, every ill-conditioned job is flagged, and 200 sampled
-    jobs (plus every ill-conditioned sum / dot) equal the oracle exactly."""
+    with status OK, the ill-conditioned jobs the twofold must catch are
+    flagged, and 200 sampled jobs plus every ill-conditioned sum / dot equal
+    the oracle exactly, flag included."""
     torch = torch_cuda()
     sched = W.serve_schedule(20000, 2000.0, seed=1)
     inst = {}
@@ -259,8 +260,12 @@ def test_full_stream_sampled_against_oracle():
         srv.close()
     assert len(got) == len(sched)
     assert all(r["status"] == 0 for r in got.values())
+    # binary64 instances at condition 1e20 and the cancelling axpy / Horner
+    # recipes always raise the flag; a binary32 twofold at condition 1e20 can
+    # itself lose track of the error (the paper's "twofolds may miss"), so
+    # those flags are left to the comparison with the oracle below
     for j, i in zip(sched, ids):
-        if j["illcond"]:
+        if j["illcond"] and (j["dtype"] == "f64" or j["op"] in ("axpy", "horner")):
             assert got[i]["flag"] == 1, j
     rng = np.random.default_rng(0)
     sample = set(rng.choice(len(sched), 200, replace=False).tolist())
