@@ -5,11 +5,13 @@
 // descriptor into its device slot and opens the slot with a release store of
 // the slot's control word.  Every other block is a worker: its first wave
 // reads the 64 control words (one per lane), picks the job with the fewest
-// unclaimed units (oldest first among equals) and claims its next unit with
-// a compare-and-swap on the control word (the generation in the word makes a
-// stale claim fail); the whole block processes the unit (a 4096-leaf
-// aligned subtree of a sum / dot, or 4096 elements of an axpy / Horner),
-// then bumps the job's done counter.  The
+// unclaimed units (oldest first among equals) and claims a unit with a
+// fetch-add on the control word (wait-free: the returned word says which
+// unit of which job the block owns, or that it came too late); the whole
+// block processes the unit (a 4096-leaf aligned subtree of a sum / dot, or
+// 4096 elements of an axpy / Horner), then bumps the job's done counter.
+// A block keeps its LDS copy of the descriptor while it keeps claiming
+// units of the same job.  The
 // block that completes a job's last unit joins the per-unit partials and
 // writes the job's completion record (generation last, system-scope
 // release).  Workers never wait for each other, so the grid needs no
@@ -402,15 +404,20 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
 }
 
 __device__ void worker(tfs_shared *sh, DevState *st) {
-    __shared__ int s_slot, s_claim, s_last;
+    __shared__ int s_slot, s_claim, s_last, s_have_slot;
+    __shared__ uint32_t s_gen, s_have_gen;
     __shared__ uint64_t s_desc[sizeof(tfs_desc) / 8];
     const int t = threadIdx.x;
+    if (t == 0) {
+        s_have_slot = -1;
+        s_have_gen = 0;
+    }
     while (true) {
         if (t < 64) {
             const uint64_t c = __hip_atomic_load(&st->slot[t].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t gen = TFS_CTL_GEN(c), nt = TFS_CTL_NTILES(c), nx = TFS_CTL_NEXT(c);
             // shortest remaining job first (fewest unclaimed units), then oldest
-            const uint64_t key = (gen != 0 && nx < nt) ? ((nt - nx) << 36) | gen : ~0ull;
+            const uint64_t key = (gen != 0 && nx < nt) ? ((nt - nx) << 32) | gen : ~0ull;
             uint64_t m = key;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
@@ -423,26 +430,41 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                     s_slot = stop ? -3 : -1;
                 }
             } else if (key == m) {  // the one lane holding the chosen job
-                uint64_t expected = c;
-                const bool ok = __hip_atomic_compare_exchange_strong(
-                    &st->slot[t].ctl, &expected, c + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // Wait-free claim: the returned word names the unit this block
+                // owns.  The slot may have been emptied or reopened for a
+                // newer job since the scan; an add past the last unit (or on
+                // an empty word, which the next opening overwrites) claims
+                // nothing, and a unit of a newer job is as good as any.
+                const uint64_t old = __hip_atomic_fetch_add(&st->slot[t].ctl, (uint64_t)1, __ATOMIC_ACQ_REL,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t g = TFS_CTL_GEN(old);
+                const bool ok = g != 0 && TFS_CTL_NEXT(old) < TFS_CTL_NTILES(old);
                 s_slot = ok ? t : -2;
-                s_claim = (int)TFS_CTL_NEXT(c);
+                s_claim = (int)TFS_CTL_NEXT(old);
+                s_gen = (uint32_t)g;
             }
         }
         __syncthreads();
         const int slot = s_slot, claim = s_claim;
+        const uint32_t gen = s_gen;
+        const bool fresh = slot >= 0 && (slot != s_have_slot || gen != s_have_gen);
         __syncthreads();
         if (slot == -3) break;
         if (slot < 0) {
             if (slot == -1) __builtin_amdgcn_s_sleep(64);
             continue;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         DevSlot *S = &st->slot[slot];
-        const uint64_t *src = (const uint64_t *)&S->d;
-        for (unsigned k = t; k < sizeof(tfs_desc) / 8; k += kBlock) s_desc[k] = src[k];
-        __syncthreads();
+        if (fresh) {  // the block's copy of the descriptor is for another job
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint64_t *src = (const uint64_t *)&S->d;
+            for (unsigned k = t; k < sizeof(tfs_desc) / 8; k += kBlock) s_desc[k] = src[k];
+            if (t == 0) {
+                s_have_slot = slot;
+                s_have_gen = gen;
+            }
+            __syncthreads();
+        }
         const tfs_desc &d = *(const tfs_desc *)s_desc;
         if (claim == 0 && t == 0) S->t_start = wall_clock64();
         if (d.dtype == TF_F64) run_claim<double>(d, claim);

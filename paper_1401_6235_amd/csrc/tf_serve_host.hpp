@@ -318,7 +318,8 @@ class Server {
             pending_.pop_front();
             s.off = off;
             s.t_admit = now_s();
-            fill_desc(s, ++gen_, slot);
+            if ((uint32_t)++gen_ == 0) ++gen_;  // the slot word keeps 32 bits; 0 means empty
+            fill_desc(s, gen_, slot);
             const uint64_t resident = pool_.capacity() - pool_.free_bytes();
             resident_ = resident;
             if (resident > peak_resident_) peak_resident_ = resident;

@@ -29,13 +29,17 @@
 #define TFS_MAX_CLAIMS 16383   /* claims per job (14-bit field) */
 #define TFS_MAX_N ((int64_t)TFS_CLAIM * TFS_MAX_CLAIMS)
 
-/* Control word of a device slot: generation (36 bits), number of claims
- * (14 bits), next unclaimed claim (14 bits).  gen == 0: slot empty. */
+/* Control word of a device slot: generation (low 32 bits of the
+ * publication number, never 0), number of claims (14 bits), next unclaimed
+ * claim (18 bits).  gen == 0: slot empty.  Workers claim with a fetch-add of
+ * 1; a worker adds only after it has seen next < claims, so the count runs
+ * past the number of claims by at most the number of workers and never
+ * reaches the claims field. */
 #define TFS_CTL(gen, ntiles, next)                                                   \
-    (((uint64_t)(gen) << 28) | ((uint64_t)(ntiles) << 14) | (uint64_t)(next))
-#define TFS_CTL_GEN(c) ((c) >> 28)
-#define TFS_CTL_NTILES(c) (((c) >> 14) & 0x3fffu)
-#define TFS_CTL_NEXT(c) ((c)&0x3fffu)
+    (((uint64_t)(uint32_t)(gen) << 32) | ((uint64_t)(ntiles) << 18) | (uint64_t)(next))
+#define TFS_CTL_GEN(c) ((c) >> 32)
+#define TFS_CTL_NTILES(c) (((c) >> 18) & 0x3fffu)
+#define TFS_CTL_NEXT(c) ((c)&0x3ffffu)
 
 typedef struct {
     uint64_t gen;      /* publication number, 1, 2, ... */
