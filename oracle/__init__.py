@@ -313,3 +313,97 @@ def ref64(op: str, *args):
     else:
         raise ValueError(op)
     return dz
+
+
+# ---- coupled algorithms, chains, applications, fma -------------------------
+
+OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4}
+MODES = {"twofold": 0, "coupled": 1, "dekker": 2}
+
+
+def fast_two_sum(a, b):
+    """Algorithm 1.1: (s, t), exact when |a| >= |b|."""
+    return _eft2("fast_two_sum", a, b)
+
+
+def coupled(op: str, x0, x1, y0=None, y1=None, renorm: bool = False):
+    """Coupled ("p") operation: ATF1 / STF1 for add and sub, MPF1, DPF1,
+    RPF1 (and their dotted forms); with ``renorm`` the result is passed
+    through Fast Two-Sum (Dekker mode)."""
+    dt = np.asarray(x0).dtype
+    x0, x1, y0, y1 = (_arr(v, dt) for v in (x0, x1, y0, y1))
+    n = x0.size
+    z0, z1 = np.empty(n, dt), np.empty(n, dt)
+    _fn("orc_coupled_" + _sfx(x0))(C.c_int(OPS[op]), C.c_int(int(renorm)), C.c_int64(n),
+                                   _p(x0), _p(x1), _p(y0), _p(y1), _p(z0), _p(z1))
+    return z0, z1
+
+
+def renorm(z0, z1):
+    """Fast Two-Sum renormalisation of each twofold."""
+    dt = np.asarray(z0).dtype
+    z0, z1 = _arr(z0, dt), _arr(z1, dt)
+    s, t = np.empty(z0.size, dt), np.empty(z0.size, dt)
+    _fn("orc_renorm_" + _sfx(z0))(C.c_int64(z0.size), _p(z0), _p(z1), _p(s), _p(t))
+    return s, t
+
+
+def chain(op: str, mode: str, reps: int, x0, x1, y0=None, y1=None):
+    """z = (x0, x1 or +0), then ``reps`` times z = z (op) y (sqrt: sqrt(z))."""
+    dt = np.asarray(x0).dtype
+    x0, x1, y0, y1 = (_arr(v, dt) for v in (x0, x1, y0, y1))
+    n = x0.size
+    z0, z1 = np.empty(n, dt), np.empty(n, dt)
+    _fn("orc_chain_" + _sfx(x0))(C.c_int(OPS[op]), C.c_int(MODES[mode]), C.c_int64(n), C.c_int64(reps),
+                                 _p(x0), _p(x1), _p(y0), _p(y1), _p(z0), _p(z1))
+    return z0, z1
+
+
+def plain_chain(op: str, reps: int, x, y=None):
+    dt = np.asarray(x).dtype
+    x, y = _arr(x, dt), _arr(y, dt)
+    z = np.empty(x.size, dt)
+    _fn("orc_plain_chain_" + _sfx(x))(C.c_int(OPS[op]), C.c_int64(x.size), C.c_int64(reps), _p(x), _p(y), _p(z))
+    return z
+
+
+def trsv_upper(m: int, U0, U1, f0, f1):
+    """Back-substitution of upper-triangular systems, systems interleaved:
+    U[(i*m + j)*nsys + k], f and x [i*nsys + k].  Returns (x0, x1)."""
+    dt = np.asarray(U0).dtype
+    U0, U1, f0, f1 = (_arr(v, dt) for v in (U0, U1, f0, f1))
+    nsys = f0.size // m
+    x0, x1 = np.empty(f0.size, dt), np.empty(f0.size, dt)
+    _fn("orc_trsv_upper_" + _sfx(U0))(C.c_int64(nsys), C.c_int(m), _p(U0), _p(U1), _p(f0), _p(f1),
+                                      _p(x0), _p(x1))
+    return x0, x1
+
+
+def quadratic(a0, a1, b0, b1, c0, c1):
+    """Both roots by the school formula; returns (r0, r1, s0, s1) with r the
+    root -b - sqrt(.) and s the root -b + sqrt(.) over 2a."""
+    dt = np.asarray(a0).dtype
+    a0, a1, b0, b1, c0, c1 = (_arr(v, dt) for v in (a0, a1, b0, b1, c0, c1))
+    n = a0.size
+    out = [np.empty(n, dt) for _ in range(4)]
+    _fn("orc_quadratic_" + _sfx(a0))(C.c_int64(n), _p(a0), _p(a1), _p(b0), _p(b1), _p(c0), _p(c1),
+                                     *[_p(o) for o in out])
+    return tuple(out)
+
+
+def fma(x0, x1, y0, y1, w0, w1):
+    """Twofold fused multiply-add z = x y + w (an extension of the paper)."""
+    dt = np.asarray(x0).dtype
+    x0, x1, y0, y1, w0, w1 = (_arr(v, dt) for v in (x0, x1, y0, y1, w0, w1))
+    n = x0.size
+    z0, z1 = np.empty(n, dt), np.empty(n, dt)
+    _fn("orc_fma_" + _sfx(x0))(C.c_int64(n), _p(x0), _p(x1), _p(y0), _p(y1), _p(w0), _p(w1), _p(z0), _p(z1))
+    return z0, z1
+
+
+def plain_fma(x, y, w):
+    dt = np.asarray(x).dtype
+    x, y, w = (_arr(v, dt) for v in (x, y, w))
+    z = np.empty(x.size, dt)
+    _fn("orc_plain_fma_" + _sfx(x))(C.c_int64(x.size), _p(x), _p(y), _p(w), _p(z))
+    return z

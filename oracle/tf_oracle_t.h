@@ -516,6 +516,279 @@ void NM(orc_accumulate)(int64_t steps, T t0, T t1, T *out)
 }
 
 /* ---------------------------------------------------------------------
+ * Coupled ("p") algorithms and renormalisation (Dekker arithmetic section;
+ * Algorithms 1.1, MPF1, DPF1, RPF1).  A coupled twofold has |z1| at most
+ * half an ulp of z0; the p-algorithms drop the terms that are negligible
+ * for such operands.  Operation codes: 0 add, 1 sub, 2 mul, 3 div, 4 sqrt.
+ * ------------------------------------------------------------------- */
+
+/* Fast Two-Sum (Algorithm 1.1), exact when |a| >= |b|:
+ * s = a (+) b; b' = s (-) a; t = b (-) b'. */
+static PAIR NM(fast_two_sum)(T a, T b)
+{
+    T s = a + b;
+    T bv = s - a;
+    PAIR r;
+    r.z0 = s;
+    r.z1 = b - bv;
+    return r;
+}
+
+TF_EFT_ARRAY2(fast_two_sum)
+
+/* MPF1: the product x1 y1 is dropped; z0 = p00; z1 = e00 (+) (p01 (+) p10). */
+static PAIR NM(mul_pp)(T x0, T x1, T y0, T y1)
+{
+    PAIR p = NM(two_prod)(x0, y0);
+    T p01 = x0 * y1;
+    T p10 = x1 * y0;
+    PAIR z;
+    z.z0 = p.z0;
+    z.z1 = p.z1 + (p01 + p10);
+    return z;
+}
+
+/* DPF1: the divisor's low part is not added back into the denominator;
+ * z0 = x0 (/) y0; r0 = fma(-z0, y0, x0); r1 = fma(-z0, y1, x1);
+ * c0 = r0 (+) r1; z1 = c0 (/) y0. */
+static PAIR NM(div_pp)(T x0, T x1, T y0, T y1)
+{
+    T z0 = x0 / y0;
+    T r0 = FMA(-z0, y0, x0);
+    T r1 = FMA(-z0, y1, x1);
+    T c0 = r0 + r1;
+    PAIR z;
+    z.z0 = z0;
+    z.z1 = c0 / y0;
+    return z;
+}
+
+/* One coupled operation.  xt / yt say whether the operand is a twofold
+ * (otherwise its low part is ignored and the dotted form applies):
+ *   add, sub: ATF1 / STF1 and their 1.1 forms, which the paper keeps for
+ *             coupled input;
+ *   mul: MPF1; one dotted operand: MPF1.1 = MTF1.1; both: Two-Product;
+ *   div: DPF1; dotted divisor: DTF1.1; dotted dividend: DPF1 with x1 = +0;
+ *        both dotted: DTF1.1.1;
+ *   sqrt: RPF1 on x; dotted: RPF1.1. */
+static PAIR NM(coupled_op)(int op, T x0, T x1, int xt, T y0, T y1, int yt)
+{
+    switch (op) {
+    case 0:
+        return xt && yt ? NM(add_tt)(x0, x1, y0, y1) : xt ? NM(add_td)(x0, x1, y0)
+               : yt ? NM(add_dt)(x0, y0, y1) : NM(add_dd)(x0, y0);
+    case 1:
+        return xt && yt ? NM(sub_tt)(x0, x1, y0, y1) : xt ? NM(sub_td)(x0, x1, y0)
+               : yt ? NM(sub_dt)(x0, y0, y1) : NM(sub_dd)(x0, y0);
+    case 2:
+        return xt && yt ? NM(mul_pp)(x0, x1, y0, y1) : xt ? NM(mul_td)(x0, x1, y0)
+               : yt ? NM(mul_dt)(x0, y0, y1) : NM(mul_dd)(x0, y0);
+    case 3:
+        return xt && yt ? NM(div_pp)(x0, x1, y0, y1) : xt ? NM(div_td)(x0, x1, y0)
+               : yt ? NM(div_pp)(x0, (T)0, y0, y1) : NM(div_dd)(x0, y0);
+    default:
+        return xt ? NM(sqrt_coupled)(x0, x1) : NM(sqrt_d)(x0);
+    }
+}
+
+/* One twofold operation of the same code, for the chains below. */
+static PAIR NM(twofold_op)(int op, T x0, T x1, T y0, T y1, int yt)
+{
+    switch (op) {
+    case 0: return yt ? NM(add_tt)(x0, x1, y0, y1) : NM(add_td)(x0, x1, y0);
+    case 1: return yt ? NM(sub_tt)(x0, x1, y0, y1) : NM(sub_td)(x0, x1, y0);
+    case 2: return yt ? NM(mul_tt)(x0, x1, y0, y1) : NM(mul_td)(x0, x1, y0);
+    case 3: return yt ? NM(div_tt)(x0, x1, y0, y1) : NM(div_td)(x0, x1, y0);
+    default: return NM(sqrt_t)(x0, x1);
+    }
+}
+
+/* Array form: z = coupled op(x, y), renormalised with Fast Two-Sum when
+ * `renorm` is set (Dekker mode: the output is then non-overlapping, and z0
+ * is no longer the standard result).  NULL low part: dotted operand. */
+void NM(orc_coupled)(int op, int renorm, int64_t n, const T *x0, const T *x1,
+                     const T *y0, const T *y1, T *z0, T *z1)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        PAIR z = NM(coupled_op)(op, x0[i], x1 ? x1[i] : (T)0, x1 != 0,
+                                op == 4 ? (T)0 : y0[i], y1 ? y1[i] : (T)0, y1 != 0);
+        if (renorm) z = NM(fast_two_sum)(z.z0, z.z1);
+        z0[i] = z.z0;
+        z1[i] = z.z1;
+    }
+}
+
+/* Renormalisation of twofolds with Fast Two-Sum: (s, t) = (z0 (+) z1, ...). */
+void NM(orc_renorm)(int64_t n, const T *z0, const T *z1, T *s, T *t)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        PAIR r = NM(fast_two_sum)(z0[i], z1[i]);
+        s[i] = r.z0;
+        t[i] = r.z1;
+    }
+}
+
+/* ---------------------------------------------------------------------
+ * Chains: one operation applied over and over to a value that stays in
+ * registers, the compute-bound regime of the performance criteria
+ * (Introduction; Performance).  For every i the state starts at
+ * z = (x0_i, x1_i), or (x0_i, +0) when x1 is NULL, and each of `reps` steps
+ * sets z = z (op) y_i (sqrt: z = sqrt(z)); y is dotted when y1 is NULL.
+ * mode 0: twofold algorithms (ATF1, STF1, MTF1, DTF1, RTF1 and the *.1
+ *         forms for a dotted y);
+ * mode 1: coupled algorithms (ATF1, STF1, MPF1, DPF1, RPF1);
+ * mode 2: Dekker mode, each coupled step followed by Fast Two-Sum.
+ * ------------------------------------------------------------------- */
+void NM(orc_chain)(int op, int mode, int64_t n, int64_t reps, const T *x0,
+                   const T *x1, const T *y0, const T *y1, T *z0, T *z1)
+{
+    int yt = y1 != 0;
+    for (int64_t i = 0; i < n; ++i) {
+        PAIR z;
+        z.z0 = x0[i];
+        z.z1 = x1 ? x1[i] : (T)0;
+        T b0 = op == 4 ? (T)0 : y0[i], b1 = yt ? y1[i] : (T)0;
+        for (int64_t k = 0; k < reps; ++k) {
+            if (mode == 0) {
+                z = NM(twofold_op)(op, z.z0, z.z1, b0, b1, yt);
+            } else {
+                z = NM(coupled_op)(op, z.z0, z.z1, 1, b0, b1, yt);
+                if (mode == 2) z = NM(fast_two_sum)(z.z0, z.z1);
+            }
+        }
+        z0[i] = z.z0;
+        z1[i] = z.z1;
+    }
+}
+
+/* Plain chain: z = x_i, then z = z (op) y_i (sqrt: sqrt(z)), `reps` times. */
+void NM(orc_plain_chain)(int op, int64_t n, int64_t reps, const T *x, const T *y, T *z)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        T v = x[i];
+        for (int64_t k = 0; k < reps; ++k) {
+            switch (op) {
+            case 0: v = v + y[i]; break;
+            case 1: v = v - y[i]; break;
+            case 2: v = v * y[i]; break;
+            case 3: v = v / y[i]; break;
+            default: v = SQRT(v);
+            }
+        }
+        z[i] = v;
+    }
+}
+
+/* ---------------------------------------------------------------------
+ * Applications, batched: many independent small problems, each solved
+ * with the twofold operations in the order the formulas give.
+ * ------------------------------------------------------------------- */
+
+/* Back-substitution for upper-triangular m x m systems U x = f
+ * (Applications, Linear Ax=f; the Jordan block is the bidiagonal case):
+ * for i = m-1 down to 0: s = f_i; for j = i+1 .. m-1:
+ * s = STF1(s, MTF1(U_ij, x_j)); then x_i = DTF1(s, U_ii).
+ * The state s and the x_j are twofolds; f_i starts as (f0, f1 or +0).  A
+ * NULL U1 makes the matrix dotted (MTF1.1 with the dotted operand first,
+ * DTF1.1).  Layout, with k the system: U entry (i, j) at
+ * [(i*m + j)*nsys + k], f_i and x_i at [i*nsys + k]. */
+void NM(orc_trsv_upper)(int64_t nsys, int m, const T *U0, const T *U1,
+                        const T *f0, const T *f1, T *x0, T *x1)
+{
+    for (int64_t k = 0; k < nsys; ++k) {
+        for (int i = m - 1; i >= 0; --i) {
+            PAIR s;
+            s.z0 = f0[(int64_t)i * nsys + k];
+            s.z1 = f1 ? f1[(int64_t)i * nsys + k] : (T)0;
+            for (int j = i + 1; j < m; ++j) {
+                int64_t a = ((int64_t)i * m + j) * nsys + k, b = (int64_t)j * nsys + k;
+                PAIR p = U1 ? NM(mul_tt)(U0[a], U1[a], x0[b], x1[b])
+                            : NM(mul_dt)(U0[a], x0[b], x1[b]);
+                s = NM(sub_tt)(s.z0, s.z1, p.z0, p.z1);
+            }
+            int64_t d = ((int64_t)i * m + i) * nsys + k;
+            PAIR x = U1 ? NM(div_tt)(s.z0, s.z1, U0[d], U1[d]) : NM(div_td)(s.z0, s.z1, U0[d]);
+            x0[(int64_t)i * nsys + k] = x.z0;
+            x1[(int64_t)i * nsys + k] = x.z1;
+        }
+    }
+}
+
+/* Roots of a x^2 + b x + c = 0 by the school formula (Applications, Square
+ * root), every operand a twofold and every step a twofold operation:
+ * q = STF1(MTF1(b, b), MTF1(MTF1((4, 0), a), c)); d = RTF1(q);
+ * e = MTF1((2, 0), a); nb = (-b0, -b1);
+ * r = DTF1(STF1(nb, d), e) and s = DTF1(ATF1(nb, d), e).
+ * A negative discriminant gives NaN, which flows into both roots. */
+void NM(orc_quadratic)(int64_t n, const T *a0, const T *a1, const T *b0, const T *b1,
+                       const T *c0, const T *c1, T *r0, T *r1, T *s0, T *s1)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        PAIR bb = NM(mul_tt)(b0[i], b1[i], b0[i], b1[i]);
+        PAIR a4 = NM(mul_tt)((T)4, (T)0, a0[i], a1[i]);
+        PAIR ac = NM(mul_tt)(a4.z0, a4.z1, c0[i], c1[i]);
+        PAIR q = NM(sub_tt)(bb.z0, bb.z1, ac.z0, ac.z1);
+        PAIR d = NM(sqrt_t)(q.z0, q.z1);
+        PAIR e = NM(mul_tt)((T)2, (T)0, a0[i], a1[i]);
+        T nb0 = -b0[i], nb1 = -b1[i];
+        PAIR u = NM(sub_tt)(nb0, nb1, d.z0, d.z1);
+        PAIR v = NM(add_tt)(nb0, nb1, d.z0, d.z1);
+        PAIR r = NM(div_tt)(u.z0, u.z1, e.z0, e.z1);
+        PAIR s = NM(div_tt)(v.z0, v.z1, e.z0, e.z1);
+        r0[i] = r.z0;
+        r1[i] = r.z1;
+        s0[i] = s.z0;
+        s1[i] = s.z1;
+    }
+}
+
+/* ---------------------------------------------------------------------
+ * Twofold fused multiply-add, z = x y + w (an extension: the paper defines
+ * the four operations and the square root only).  z0 = fma(x0, y0, w0) is
+ * the standard result; the error of that fma, x0 y0 + w0 - z0, is the sum
+ * of two floats (Boldo and Muller, "Exact and approximated error of the
+ * FMA", IEEE TC 2011) and its rounded value eps = r2 comes from their
+ * ErrFma steps:
+ *   (u1, u2) = TP(x0, y0); (a1, a2) = TS(w0, u2); (b1, b2) = TS(u1, a1);
+ *   g = (b1 (-) z0) (+) b2; r2 = g (+) a2.
+ * The remaining terms follow MTF1 and ATF1:
+ *   z1 = ((eps (+) p11) (+) (p01 (+) p10)) (+) w1,
+ * with the products of an absent (dotted) low part left out. */
+static PAIR NM(fma_t)(T x0, T x1, int xt, T y0, T y1, int yt, T w0, T w1, int wt)
+{
+    T z0 = FMA(x0, y0, w0);
+    PAIR u = NM(two_prod)(x0, y0);
+    PAIR a = NM(two_sum)(w0, u.z1);
+    PAIR b = NM(two_sum)(u.z0, a.z0);
+    T g = (b.z0 - z0) + b.z1;
+    T eps = g + a.z1;
+    T t = eps;
+    if (xt && yt) t = (t + x1 * y1) + (x0 * y1 + x1 * y0);
+    else if (xt) t = t + x1 * y0;
+    else if (yt) t = t + x0 * y1;
+    if (wt) t = t + w1;
+    PAIR z;
+    z.z0 = z0;
+    z.z1 = t;
+    return z;
+}
+
+void NM(orc_fma)(int64_t n, const T *x0, const T *x1, const T *y0, const T *y1,
+                 const T *w0, const T *w1, T *z0, T *z1)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        PAIR z = NM(fma_t)(x0[i], x1 ? x1[i] : (T)0, x1 != 0, y0[i], y1 ? y1[i] : (T)0,
+                           y1 != 0, w0[i], w1 ? w1[i] : (T)0, w1 != 0);
+        z0[i] = z.z0;
+        z1[i] = z.z1;
+    }
+}
+
+/* The plain fma, the standard result the twofold one extends. */
+void NM(orc_plain_fma)(int64_t n, const T *x, const T *y, const T *w, T *z)
+{ for (int64_t i = 0; i < n; ++i) z[i] = FMA(x[i], y[i], w[i]); }
+
+/* ---------------------------------------------------------------------
  * Plain (dotted-only) counterparts: the standard results, the same
  * operation order as the z0 part of the twofold forms.
  * ------------------------------------------------------------------- */

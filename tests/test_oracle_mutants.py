@@ -12,7 +12,9 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_apps as A
 import test_oracle_bounds as B
+import test_oracle_coupled as CP
 import test_oracle_eft as E
 import test_oracle_paper as P
 import test_oracle_tree as T
@@ -44,16 +46,16 @@ MUTANTS = [
      "z.z1 = p.z1 + (p01 + p10);",
      [lambda: B.test_general_twofold_bound("mul", F64)]),
     ("mtf1_exchanged_operand",
-     "T p10 = x1 * y0;",
-     "T p10 = x1 * y1;",
+     "T p10 = x1 * y0;\n    T p11 = x1 * y1;",
+     "T p10 = x1 * y1;\n    T p11 = x1 * y1;",
      [lambda: B.test_general_twofold_bound("mul", F64)]),
     ("mtf1_dropped_e00",
      "z.z1 = (p.z1 + p11) + (p01 + p10);",
      "z.z1 = p11 + (p01 + p10);",
      [lambda: B.test_general_twofold_bound("mul", F64)]),
     ("dtf1_dropped_r1",
-     "T c0 = r0 + r1;",
-     "T c0 = r0;",
+     "T c0 = r0 + r1;\n    T d0 = y0 + y1;",
+     "T c0 = r0;\n    T d0 = y0 + y1;",
      [lambda: B.test_general_twofold_bound("div", F64)]),
     ("dtf1_divisor_not_renormalised",
      "T d0 = y0 + y1;",
@@ -99,6 +101,50 @@ MUTANTS = [
      "T b_lost = b - b_virt;  /* what b lost in the rounding */",
      "T b_lost = b_virt - b;  /* what b lost in the rounding */",
      [lambda: E.test_two_sum_is_exact(F32)]),
+    ("fast_two_sum_lost_part_sign",
+     "r.z1 = b - bv;",
+     "r.z1 = bv - b;",
+     [lambda: CP.test_fast_two_sum_is_exact_when_ordered(F64)]),
+    ("mpf1_keeps_p11",
+     "z.z1 = p.z1 + (p01 + p10);\n    return z;\n}\n\n/* DPF1",
+     "z.z1 = (p.z1 + x1 * y1) + (p01 + p10);\n    return z;\n}\n\n/* DPF1",
+     [lambda: CP.test_mpf1_exact_cases(F64)]),
+    ("mpf1_dropped_p10",
+     "z.z1 = p.z1 + (p01 + p10);\n    return z;\n}\n\n/* DPF1",
+     "z.z1 = p.z1 + p01;\n    return z;\n}\n\n/* DPF1",
+     [lambda: CP.test_mpf1_bound_on_coupled_operands(F64)]),
+    ("dpf1_divides_by_the_full_divisor",
+     "z.z1 = c0 / y0;\n    return z;\n}\n\n/* One coupled",
+     "z.z1 = c0 / (y0 + y1);\n    return z;\n}\n\n/* One coupled",
+     [lambda: CP.test_dpf1_exact_cases(F64)]),
+    ("dpf1_r1_sign",
+     "T r1 = FMA(-z0, y1, x1);\n    T c0 = r0 + r1;\n    PAIR z;",
+     "T r1 = FMA(z0, y1, x1);\n    T c0 = r0 + r1;\n    PAIR z;",
+     [lambda: CP.test_dpf1_bound_on_coupled_operands(F64)]),
+    ("dekker_chain_skips_renormalising",
+     "if (mode == 2) z = NM(fast_two_sum)(z.z0, z.z1);",
+     "if (mode == 3) z = NM(fast_two_sum)(z.z0, z.z1);",
+     [CP.test_counting_ones_saturates_without_renormalising]),
+    ("trsv_adds_the_product",
+     "s = NM(sub_tt)(s.z0, s.z1, p.z0, p.z1);",
+     "s = NM(add_tt)(s.z0, s.z1, p.z0, p.z1);",
+     [lambda: A.test_jordan_block_logs_through_the_batched_solver("double")]),
+    ("trsv_wrong_row_index",
+     "int64_t a = ((int64_t)i * m + j) * nsys + k, b = (int64_t)j * nsys + k;",
+     "int64_t a = ((int64_t)j * m + i) * nsys + k, b = (int64_t)j * nsys + k;",
+     [lambda: A.test_exact_systems_are_solved_exactly(4, F64)]),
+    ("quadratic_wrong_constant",
+     "PAIR a4 = NM(mul_tt)((T)4, (T)0, a0[i], a1[i]);",
+     "PAIR a4 = NM(mul_tt)((T)2, (T)0, a0[i], a1[i]);",
+     [lambda: A.test_integer_roots_are_exact(F64)]),
+    ("fma_error_sign",
+     "T g = (b.z0 - z0) + b.z1;",
+     "T g = (z0 - b.z0) + b.z1;",
+     [lambda: A.test_fma_error_is_rounded_exactly(F64)]),
+    ("fma_dropped_addend_low_part",
+     "if (wt) t = t + w1;",
+     "if (wt) t = t;",
+     [lambda: A.test_fma_bound("ttt", F64)]),
 ]
 
 # helper injected for the node-error mutant: ATF1 without err(x0 + y0)
@@ -117,9 +163,10 @@ def build_mutant(tmp_path, original, planted):
     body = open(os.path.join(SRC, "tf_oracle_t.h")).read()
     top = open(os.path.join(SRC, "tf_oracle.c")).read()
     if original in body:
+        assert body.count(original) == 1 or original == planted, "mutant anchor not unique"
         body = body.replace(original, planted, 1)
     else:
-        assert original in top, "mutant anchor not found"
+        assert top.count(original) == 1, "mutant anchor not found or not unique"
         top = top.replace(original, planted)
     if "plainish_add" in planted:
         anchor = "#define TF_TILE 256"
