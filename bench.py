@@ -313,6 +313,133 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
     }
 
 
+# ---------------------------------------------------------------------------
+# In-register regime (the paper's "data in cache" criterion) and the batched
+# applications
+# ---------------------------------------------------------------------------
+
+CHAIN_N = 1 << 21
+CHAIN_REPS = 256
+FP_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector FP64 / FP32, published
+# Algorithmic floating-point operations of one chain step, counting each
+# + - * / sqrt as one and each fma as two (the convention of the peaks).
+# TS = 6, TP = 3 (a multiply and an fma), Fast Two-Sum = 3.
+STEP_FLOPS = {
+    ("add", "twofold", True): 8, ("add", "twofold", False): 7,
+    ("sub", "twofold", True): 8, ("sub", "twofold", False): 7,
+    ("mul", "twofold", True): 9, ("mul", "twofold", False): 5,
+    ("div", "twofold", True): 8, ("div", "twofold", False): 5,
+    ("sqrt", "twofold", True): 21,
+    ("add", "coupled", True): 8, ("sub", "coupled", True): 8, ("mul", "coupled", True): 7,
+    ("div", "coupled", True): 7, ("sqrt", "coupled", True): 6,
+}
+TRSV_NSYS, TRSV_M = 1 << 16, 16
+QUAD_N = 1 << 24
+FMA_N = 1 << 26
+
+
+def time_call(torch, fn, steps, warmup):
+    """Average HIP-event duration (ms) of fn() on the current stream."""
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / steps
+
+
+def in_register_run(torch, tf, W, steps=3, warmup=1):
+    """Chains of CHAIN_REPS steps on CHAIN_N elements held in registers:
+    twofold (twofold and dotted operand), coupled and Dekker mode against
+    the plain chain.  The paper's criterion is twofold/plain <= 10 here."""
+    import numpy as np
+    out = {"n": CHAIN_N, "reps": CHAIN_REPS, "ops": {}}
+    for dt, tag in ((np.float64, "f64"), (np.float32, "f32")):
+        for op in ("add", "sub", "mul", "div", "sqrt"):
+            c = W.chain_case(op, CHAIN_N, seed=0, dtype=dt)
+            g = {k: torch.from_numpy(v).cuda() for k, v in c.items()}
+            z0, z1 = torch.empty_like(g["x0"]), torch.empty_like(g["x0"])
+            y0, y1 = g.get("y0"), g.get("y1")
+            plain = time_call(torch, lambda: tf.tf_plain_chain(op, CHAIN_REPS, g["x0"], y0, z0), steps, warmup)
+            row = {"plain_ms": round(plain, 4)}
+            variants = [("twofold", True), ("coupled", True), ("dekker", True)]
+            if op != "sqrt":
+                variants.insert(1, ("twofold", False))
+            for mode, yt in variants:
+                ms = time_call(torch, lambda: tf.tf_chain(op, mode, CHAIN_REPS, g["x0"], g["x1"], y0,
+                                                          y1 if yt else None, z0, z1), steps, warmup)
+                key = mode if yt else mode + "_dotted_y"
+                flops = STEP_FLOPS.get((op, "coupled" if mode == "dekker" else mode, yt))
+                if flops is not None and mode == "dekker":
+                    flops += 3
+                steps_s = CHAIN_N * CHAIN_REPS / (ms * 1e-3)
+                row[key] = {"ms": round(ms, 4), "gop_s": round(steps_s / 1e9, 1),
+                            "slowdown": round(ms / plain, 2)}
+                if flops is not None:
+                    tfl = flops * steps_s / 1e12
+                    row[key]["tflop_s"] = round(tfl, 2)
+                    row[key]["frac_fp_peak"] = round(tfl / FP_PEAK_TFLOPS[tag], 4)
+            row["plain_gop_s"] = round(CHAIN_N * CHAIN_REPS / (plain * 1e-3) / 1e9, 1)
+            out["ops"]["%s_%s" % (op, tag)] = row
+            del g, z0, z1
+    worst = max(v["twofold"]["slowdown"] for v in out["ops"].values())
+    out["max_twofold_slowdown"] = worst
+    out["meets_10x"] = worst <= 10.0
+    return out
+
+
+def applications_run(torch, tf, W, steps=3, warmup=1):
+    """Batched back-substitution (dense upper-triangular, m = 16, 2^16
+    systems), both quadratic roots (n = 2^24) and the twofold fma
+    (n = 2^26): time, HBM rate of the algorithmic bytes, slowdown against
+    the plain kernels."""
+    import numpy as np
+    out = {}
+    for dt, tag, es in ((np.float64, "f64", 8), (np.float32, "f32", 4)):
+        m, ns = TRSV_M, TRSV_NSYS
+        c = W.trsv_case(m, ns, seed=0, dtype=dt, kind="dense")
+        g = {k: torch.from_numpy(v).cuda() for k, v in c.items() if k != "m"}
+        x0, x1 = torch.empty_like(g["f0"]), torch.empty_like(g["f0"])
+        ms = time_call(torch, lambda: tf.tf_trsv_upper(m, g["U0"], g["U1"], g["f0"], g["f1"], x0, x1), steps, warmup)
+        pms = time_call(torch, lambda: tf.tf_plain_trsv_upper(m, g["U0"], g["f0"], x0), steps, warmup)
+        alg = (m * (m + 1) // 2 * 2 + 4 * m) * es * ns  # upper U twofold, f and x twofold
+        out["trsv_" + tag] = {"nsys": ns, "m": m, "ms": round(ms, 4), "plain_ms": round(pms, 4),
+                              "gb_s": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                              "slowdown": round(ms / pms, 3)}
+        del g, x0, x1
+        q = W.quadratic_case(QUAD_N, seed=0, dtype=dt)
+        g = {k: torch.from_numpy(v).cuda() for k, v in q.items()}
+        outs = tuple(torch.empty_like(g["a0"]) for _ in range(4))
+        keys = ("a0", "a1", "b0", "b1", "c0", "c1")
+        ms = time_call(torch, lambda: tf.tf_quadratic(*[g[k] for k in keys], out=outs), steps, warmup)
+        pms = time_call(torch, lambda: tf.tf_plain_quadratic(g["a0"], g["b0"], g["c0"], outs[0], outs[1]),
+                        steps, warmup)
+        alg = 10 * es * QUAD_N
+        out["quadratic_" + tag] = {"n": QUAD_N, "ms": round(ms, 4), "plain_ms": round(pms, 4),
+                                   "gb_s": round(alg / ms / 1e6, 1),
+                                   "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                   "slowdown": round(ms / pms, 3)}
+        del g, outs
+        f = W.fma_case(FMA_N, seed=0, dtype=dt)
+        g = {k: torch.from_numpy(v).cuda() for k, v in f.items()}
+        del f
+        z0, z1 = torch.empty_like(g["x0"]), torch.empty_like(g["x0"])
+        keys = ("x0", "x1", "y0", "y1", "w0", "w1")
+        ms = time_call(torch, lambda: tf.tf_fma(*[g[k] for k in keys], z0, z1), steps, warmup)
+        pms = time_call(torch, lambda: tf.tf_plain_fma(g["x0"], g["y0"], g["w0"], z0), steps, warmup)
+        alg = 8 * es * FMA_N
+        out["fma_" + tag] = {"n": FMA_N, "ms": round(ms, 4), "plain_ms": round(pms, 4),
+                             "gb_s": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                             "slowdown": round(ms / pms, 3)}
+        del g, z0, z1
+        torch.cuda.empty_cache()
+    return out
+
+
 # rocprofv3 kernel names -> bench keys
 _OPS = {"0": "add", "1": "sub", "2": "mul", "3": "div", "4": "sqrt"}
 
@@ -404,6 +531,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the in-register chains and the batched applications")
     ap.add_argument("--serve-jobs", type=int, default=20000,
                     help="jobs in the serving stream (0 skips it)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -513,10 +642,15 @@ def main():
         "kernels": kernels,
         "kernel_source_hash": src_hash,
     }
+    # the timed passes' buffers are no longer needed
+    del inputs, tcalls, pcalls
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        log("in-register chains (n = 2^21, %d steps)" % CHAIN_REPS)
+        result["in_register"] = in_register_run(torch, tf, W)
+        log("batched applications and fma")
+        result["applications"] = applications_run(torch, tf, W)
     if args.serve_jobs > 0:
-        # the timed passes' buffers are no longer needed
-        del inputs, tcalls, pcalls
-        torch.cuda.empty_cache()
         result["serving"] = serving_run(torch, W, jobs=args.serve_jobs)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")

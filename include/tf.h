@@ -182,6 +182,109 @@ int tf_plain_dot(int dtype, int64_t n, const void *x, const void *y, void *out, 
 int tf_vmem(int dtype, int64_t n, const void *x, const void *y, void *z, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Coupled ("p") algorithms and Dekker mode (Dekker arithmetic section;
+ * Algorithms 1.1, MPF1, DPF1, RPF1).  A coupled twofold has |z1| at most
+ * half an ulp of z0 (the result of a renormalisation); the p-algorithms
+ * drop the terms that are negligible for such operands.
+ * ---------------------------------------------------------------------- */
+
+/* Operation codes of tf_coupled and tf_chain. */
+#define TF_OP_ADD 0
+#define TF_OP_SUB 1
+#define TF_OP_MUL 2
+#define TF_OP_DIV 3
+#define TF_OP_SQRT 4
+
+/* z_i = x_i op y_i with the coupled algorithm of op: ATF1 / STF1 for add and
+ * subtract (the paper keeps the fast twofold algorithms for coupled input);
+ * MPF1 for multiply, z1 = e00 + (x0 y1 + x1 y0) (x1 y1 dropped); DPF1 for
+ * divide, z1 = (r0 + r1) / y0 (y1 not added to the divisor); RPF1 for the
+ * square root (one Newton step on the pair, no renormalisation first).
+ * Dotted operands give the same forms as the twofold calls (MPF1.1 is
+ * MTF1.1, DPF1.1 is DTF1.1, RPF1.1 as tf_sqrt); a dotted dividend over a
+ * twofold divisor is DPF1 with x1 = +0.  renorm != 0 passes every result
+ * through Fast Two-Sum (Algorithm 1.1), the Dekker mode: the output is then
+ * coupled and z0 is the rounded value of the pair, no longer the standard
+ * result.  y0 / y1 are ignored for TF_OP_SQRT.  Other arguments as tf_add;
+ * TF_EINVAL for an unknown op. */
+int tf_coupled(int dtype, int op, int renorm, int64_t n, const void *x0, const void *x1,
+               const void *y0, const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Renormalise twofolds with Fast Two-Sum (Algorithm 1.1):
+ * s_i = z0_i + z1_i, t_i = z1_i - (s_i - z0_i); exact (s + t = z0 + z1) when
+ * |z0_i| >= |z1_i|, computed literally otherwise.  z0, z1 required; s and t
+ * may alias them exactly. */
+int tf_renorm(int dtype, int64_t n, const void *z0, const void *z1, void *s, void *t,
+              hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Chains: the compute-bound regime of the paper's performance criteria
+ * (Introduction; Performance: the "10x" criterion for data already in
+ * cache).  For each i the state starts at z = (x0_i, x1_i), or (x0_i, +0)
+ * when x1 is NULL, and `reps` times z = z op y_i (TF_OP_SQRT: z = sqrt(z)),
+ * the value staying in registers; y is dotted when y1 is NULL.
+ *   mode TF_MODE_TWOFOLD  ATF1, STF1, MTF1, DTF1, RTF1 (and the *.1 forms for
+ *                         a dotted y);
+ *   mode TF_MODE_COUPLED  ATF1, STF1, MPF1, DPF1, RPF1;
+ *   mode TF_MODE_DEKKER   the coupled step followed by Fast Two-Sum (the
+ *                         paper's renormalising accumulator).
+ * reps >= 0 (0 copies the start value).  HBM traffic is one read of each
+ * input and one write of each output; the rest is arithmetic. */
+#define TF_MODE_TWOFOLD 0
+#define TF_MODE_COUPLED 1
+#define TF_MODE_DEKKER 2
+int tf_chain(int dtype, int op, int mode, int64_t n, int64_t reps, const void *x0, const void *x1,
+             const void *y0, const void *y1, void *z0, void *z1, hipStream_t stream);
+
+/* Plain chain: z_i = x_i, then reps times z_i = z_i op y_i (sqrt: sqrt(z_i)). */
+int tf_plain_chain(int dtype, int op, int64_t n, int64_t reps, const void *x, const void *y, void *z,
+                   hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Applications, batched (Applications section): many independent small
+ * problems, one per GPU thread.
+ * ---------------------------------------------------------------------- */
+
+/* Back-substitution of nsys upper-triangular m x m systems U x = f
+ * (Applications, Linear Ax=f; the paper's Jordan block is the bidiagonal
+ * case), 1 <= m <= TF_MAX_TRSV: for i = m-1 down to 0, s = (f0, f1 or +0);
+ * for j = i+1 .. m-1, s = STF1(s, MTF1(U_ij, x_j)); x_i = DTF1(s, U_ii).  A
+ * NULL U1 makes the matrix dotted (MTF1.1 with U first, DTF1.1).  Entries
+ * below the diagonal are never read.  Layout, k the system: U entry (i, j)
+ * at [(i*m + j)*nsys + k]; f_i and x_i at [i*nsys + k].  x0 / x1 must not
+ * overlap U or f. */
+#define TF_MAX_TRSV 64
+int tf_trsv_upper(int dtype, int64_t nsys, int m, const void *U0, const void *U1, const void *f0,
+                  const void *f1, void *x0, void *x1, hipStream_t stream);
+int tf_plain_trsv_upper(int dtype, int64_t nsys, int m, const void *U, const void *f, void *x,
+                        hipStream_t stream);
+
+/* Both roots of a_i x^2 + b_i x + c_i = 0 by the school formula
+ * (Applications, Square root), every operand twofold (all six arrays
+ * required): q = STF1(MTF1(b, b), MTF1(MTF1((4, 0), a), c)); d = RTF1(q);
+ * e = MTF1((2, 0), a); r = DTF1(STF1(-b, d), e); s = DTF1(ATF1(-b, d), e).
+ * A negative discriminant gives NaN in d and both roots; a zero one gives a
+ * NaN error part (RTF1 at 0). */
+int tf_quadratic(int dtype, int64_t n, const void *a0, const void *a1, const void *b0,
+                 const void *b1, const void *c0, const void *c1, void *r0, void *r1, void *s0,
+                 void *s1, hipStream_t stream);
+int tf_plain_quadratic(int dtype, int64_t n, const void *a, const void *b, const void *c, void *r,
+                       void *s, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Twofold fused multiply-add z_i = x_i y_i + w_i (an extension: the paper
+ * defines + - * / and sqrt only).  z0 = fma(x0, y0, w0), bitwise the
+ * hardware result; the error of that fma is rounded exactly with Boldo and
+ * Muller's ErrFma steps (Two-Product of x0 y0, two Two-Sums); then
+ * z1 = ((eps + x1 y1) + (x0 y1 + x1 y0)) + w1, the terms of an absent low
+ * part left out.  x1, y1, w1 may each be NULL (dotted).
+ * ---------------------------------------------------------------------- */
+int tf_fma(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           const void *w0, const void *w1, void *z0, void *z1, hipStream_t stream);
+int tf_plain_fma(int dtype, int64_t n, const void *x, const void *y, const void *w, void *z,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Launch tuning (process-wide).  Results never depend on these settings.
  *   TF_CFG_EW_BLOCKS_PER_CU    cap on the elementwise grid, in blocks per
  *                              compute unit (0 = one block per 256 threads'

@@ -24,6 +24,9 @@ TF_OK = 0
 TF_MAX_DEGREE = 32
 TF_CFG_EW_BLOCKS_PER_CU = 1
 TF_CFG_RED_TILES_PER_BLOCK = 2
+TF_MAX_TRSV = 64
+TF_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4}
+TF_MODES = {"twofold": 0, "coupled": 1, "dekker": 2}
 
 _lib = None
 
@@ -303,3 +306,116 @@ def tf_config(key: int, value: int) -> int:
     if old < 0:
         raise TwofoldError("tf_config(%d, %d): invalid key or value" % (key, value))
     return old
+
+
+# ---------------------------------------------------------------------------
+# coupled algorithms, renormalisation, chains
+# ---------------------------------------------------------------------------
+
+def tf_coupled(op, x0, x1, y0=None, y1=None, renorm=False, z0=None, z1=None, stream=None):
+    """Coupled operation (ATF1, STF1, MPF1, DPF1, RPF1); ``renorm`` adds Fast
+    Two-Sum (Dekker mode).  ``op`` is "add", "sub", "mul", "div" or "sqrt"."""
+    n = x0.numel()
+    z0, z1 = _out(z0, x0), _out(z1, x0)
+    st = lib().tf_coupled(C.c_int(_dtype_code(x0)), C.c_int(TF_OPS[op]), C.c_int(int(bool(renorm))),
+                          C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype), _ptr(y0, n, x0.dtype),
+                          _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype), _stream(stream))
+    _check(st, "tf_coupled")
+    return z0, z1
+
+
+def tf_renorm(z0, z1, s=None, t=None, stream=None):
+    """Fast Two-Sum renormalisation of each twofold."""
+    n = z0.numel()
+    s, t = _out(s, z0), _out(t, z0)
+    st = lib().tf_renorm(C.c_int(_dtype_code(z0)), C.c_int64(n), _ptr(z0, n), _ptr(z1, n, z0.dtype),
+                         _ptr(s, n, z0.dtype), _ptr(t, n, z0.dtype), _stream(stream))
+    _check(st, "tf_renorm")
+    return s, t
+
+
+def tf_chain(op, mode, reps, x0, x1, y0=None, y1=None, z0=None, z1=None, stream=None):
+    """z = (x0, x1 or +0), then ``reps`` times z = z op y (sqrt: sqrt(z)),
+    in registers; ``mode`` is "twofold", "coupled" or "dekker"."""
+    n = x0.numel()
+    z0, z1 = _out(z0, x0), _out(z1, x0)
+    st = lib().tf_chain(C.c_int(_dtype_code(x0)), C.c_int(TF_OPS[op]), C.c_int(TF_MODES[mode]), C.c_int64(n),
+                        C.c_int64(reps), _ptr(x0, n), _ptr(x1, n, x0.dtype), _ptr(y0, n, x0.dtype),
+                        _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype), _stream(stream))
+    _check(st, "tf_chain")
+    return z0, z1
+
+
+def tf_plain_chain(op, reps, x, y=None, z=None, stream=None):
+    n = x.numel()
+    z = _out(z, x)
+    st = lib().tf_plain_chain(C.c_int(_dtype_code(x)), C.c_int(TF_OPS[op]), C.c_int64(n), C.c_int64(reps),
+                              _ptr(x, n), _ptr(y, n, x.dtype), _ptr(z, n, x.dtype), _stream(stream))
+    _check(st, "tf_plain_chain")
+    return z
+
+
+# ---------------------------------------------------------------------------
+# applications
+# ---------------------------------------------------------------------------
+
+def tf_trsv_upper(m, U0, U1, f0, f1=None, x0=None, x1=None, stream=None):
+    """Back-substitution of upper-triangular m x m systems, interleaved:
+    U[(i*m + j)*nsys + k], f and x [i*nsys + k]."""
+    nsys = f0.numel() // m
+    x0, x1 = _out(x0, f0), _out(x1, f0)
+    st = lib().tf_trsv_upper(C.c_int(_dtype_code(f0)), C.c_int64(nsys), C.c_int(m),
+                             _ptr(U0, m * m * nsys, f0.dtype), _ptr(U1, m * m * nsys, f0.dtype),
+                             _ptr(f0, m * nsys), _ptr(f1, m * nsys, f0.dtype), _ptr(x0, m * nsys, f0.dtype),
+                             _ptr(x1, m * nsys, f0.dtype), _stream(stream))
+    _check(st, "tf_trsv_upper")
+    return x0, x1
+
+
+def tf_plain_trsv_upper(m, U, f, x=None, stream=None):
+    nsys = f.numel() // m
+    x = _out(x, f)
+    st = lib().tf_plain_trsv_upper(C.c_int(_dtype_code(f)), C.c_int64(nsys), C.c_int(m),
+                                   _ptr(U, m * m * nsys, f.dtype), _ptr(f, m * nsys), _ptr(x, m * nsys, f.dtype),
+                                   _stream(stream))
+    _check(st, "tf_plain_trsv_upper")
+    return x
+
+
+def tf_quadratic(a0, a1, b0, b1, c0, c1, out=None, stream=None):
+    """Both roots (r0, r1, s0, s1) of a x^2 + b x + c = 0, twofold operands."""
+    n = a0.numel()
+    out = tuple(_out(None, a0) for _ in range(4)) if out is None else out
+    st = lib().tf_quadratic(C.c_int(_dtype_code(a0)), C.c_int64(n),
+                            *[_ptr(v, n, a0.dtype) for v in (a0, a1, b0, b1, c0, c1)],
+                            *[_ptr(v, n, a0.dtype) for v in out], _stream(stream))
+    _check(st, "tf_quadratic")
+    return out
+
+
+def tf_plain_quadratic(a, b, c, r=None, s=None, stream=None):
+    n = a.numel()
+    r, s = _out(r, a), _out(s, a)
+    st = lib().tf_plain_quadratic(C.c_int(_dtype_code(a)), C.c_int64(n),
+                                  *[_ptr(v, n, a.dtype) for v in (a, b, c, r, s)], _stream(stream))
+    _check(st, "tf_plain_quadratic")
+    return r, s
+
+
+def tf_fma(x0, x1, y0, y1, w0, w1, z0=None, z1=None, stream=None):
+    """Twofold fused multiply-add z = x y + w; None low parts are dotted."""
+    n = x0.numel()
+    z0, z1 = _out(z0, x0), _out(z1, x0)
+    st = lib().tf_fma(C.c_int(_dtype_code(x0)), C.c_int64(n),
+                      *[_ptr(v, n, x0.dtype) for v in (x0, x1, y0, y1, w0, w1, z0, z1)], _stream(stream))
+    _check(st, "tf_fma")
+    return z0, z1
+
+
+def tf_plain_fma(x, y, w, z=None, stream=None):
+    n = x.numel()
+    z = _out(z, x)
+    st = lib().tf_plain_fma(C.c_int(_dtype_code(x)), C.c_int64(n),
+                            *[_ptr(v, n, x.dtype) for v in (x, y, w, z)], _stream(stream))
+    _check(st, "tf_plain_fma")
+    return z

@@ -239,4 +239,129 @@ int tf_plain_dot(int dtype, int64_t n, const void *x, const void *y, void *out, 
     return reduce(LEAF_PDOT, dtype, n, x, nullptr, y, nullptr, out, work, work_bytes, stream);
 }
 
-}  // extern "C"
+// ---- coupled algorithms, renormalisation ----------------------------------------
+
+static int unary(int op, int dtype, int64_t n, const void *x0, const void *x1, void *z0, void *z1,
+                 hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && z0 && z1);
+    const Launch L = make_launch(stream, {x0, x1, z0, z1});
+    if (dtype == TF_F64) run_elementwise<double>(L, op, n, x0, x1, nullptr, nullptr, z0, z1);
+    else run_elementwise<float>(L, op, n, x0, x1, nullptr, nullptr, z0, z1);
+    return finish();
+}
+
+int tf_coupled(int dtype, int op, int renorm, int64_t n, const void *x0, const void *x1, const void *y0,
+               const void *y1, void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(op >= TF_OP_ADD && op <= TF_OP_SQRT);
+    const int code = chain_code(op, renorm ? TF_MODE_DEKKER : TF_MODE_COUPLED);
+    if (op == TF_OP_SQRT) return unary(code, dtype, n, x0, x1, z0, z1, stream);
+    return binary(code, dtype, n, x0, x1, y0, y1, z0, z1, stream);
+}
+
+int tf_renorm(int dtype, int64_t n, const void *z0, const void *z1, void *s, void *t, hipStream_t stream) {
+    if (n > 0) TF_CHECK(z1);
+    return unary(OP_FAST_TWO_SUM, dtype, n, z0, z1, s, t, stream);
+}
+
+// ---- chains --------------------------------------------------------------------------
+
+int tf_chain(int dtype, int op, int mode, int64_t n, int64_t reps, const void *x0, const void *x1,
+             const void *y0, const void *y1, void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && reps >= 0 && op >= TF_OP_ADD && op <= TF_OP_SQRT);
+    TF_CHECK(mode == TF_MODE_TWOFOLD || mode == TF_MODE_COUPLED || mode == TF_MODE_DEKKER);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && z0 && z1 && (y0 || op == TF_OP_SQRT));
+    const Launch L = make_launch(stream, {});
+    const int code = chain_code(op, mode);
+    if (dtype == TF_F64) run_chain<double>(L, code, n, reps, x0, x1, y0, y1, z0, z1);
+    else run_chain<float>(L, code, n, reps, x0, x1, y0, y1, z0, z1);
+    return finish();
+}
+
+int tf_plain_chain(int dtype, int op, int64_t n, int64_t reps, const void *x, const void *y, void *z,
+                   hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0 && reps >= 0 && op >= TF_OP_ADD && op <= TF_OP_SQRT);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x && z && (y || op == TF_OP_SQRT));
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_plain_chain<double>(L, op, n, reps, x, y, z);
+    else run_plain_chain<float>(L, op, n, reps, x, y, z);
+    return finish();
+}
+
+// ---- applications ----------------------------------------------------------------------
+
+int tf_trsv_upper(int dtype, int64_t nsys, int m, const void *U0, const void *U1, const void *f0,
+                  const void *f1, void *x0, void *x1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && nsys >= 0 && m >= 1 && m <= TF_MAX_TRSV);
+    if (nsys == 0) return TF_OK;
+    TF_CHECK(U0 && f0 && x0 && x1);
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_trsv<double>(L, nsys, m, U0, U1, f0, f1, x0, x1);
+    else run_trsv<float>(L, nsys, m, U0, U1, f0, f1, x0, x1);
+    return finish();
+}
+
+int tf_plain_trsv_upper(int dtype, int64_t nsys, int m, const void *U, const void *f, void *x,
+                        hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && nsys >= 0 && m >= 1 && m <= TF_MAX_TRSV);
+    if (nsys == 0) return TF_OK;
+    TF_CHECK(U && f && x);
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_plain_trsv<double>(L, nsys, m, U, f, x);
+    else run_plain_trsv<float>(L, nsys, m, U, f, x);
+    return finish();
+}
+
+int tf_quadratic(int dtype, int64_t n, const void *a0, const void *a1, const void *b0, const void *b1,
+                 const void *c0, const void *c1, void *r0, void *r1, void *s0, void *s1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(a0 && a1 && b0 && b1 && c0 && c1 && r0 && r1 && s0 && s1);
+    const void *in[6] = {a0, a1, b0, b1, c0, c1};
+    void *out[4] = {r0, r1, s0, s1};
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_quadratic<double>(L, n, in, out);
+    else run_quadratic<float>(L, n, in, out);
+    return finish();
+}
+
+int tf_plain_quadratic(int dtype, int64_t n, const void *a, const void *b, const void *c, void *r, void *s,
+                       hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(a && b && c && r && s);
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_plain_quadratic<double>(L, n, a, b, c, r, s);
+    else run_plain_quadratic<float>(L, n, a, b, c, r, s);
+    return finish();
+}
+
+// ---- fma -------------------------------------------------------------------------------
+
+int tf_fma(int dtype, int64_t n, const void *x0, const void *x1, const void *y0, const void *y1,
+           const void *w0, const void *w1, void *z0, void *z1, hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x0 && y0 && w0 && z0 && z1);
+    const void *in[6] = {x0, x1, y0, y1, w0, w1};
+    const Launch L = make_launch(stream, {x0, x1, y0, y1, w0, w1, z0, z1});
+    if (dtype == TF_F64) run_fma<double>(L, n, in, z0, z1);
+    else run_fma<float>(L, n, in, z0, z1);
+    return finish();
+}
+
+int tf_plain_fma(int dtype, int64_t n, const void *x, const void *y, const void *w, void *z,
+                 hipStream_t stream) {
+    TF_CHECK(size_of(dtype) && n >= 0);
+    if (n == 0) return TF_OK;
+    TF_CHECK(x && y && w && z);
+    const Launch L = make_launch(stream, {});
+    if (dtype == TF_F64) run_plain_fma<double>(L, n, x, y, w, z);
+    else run_plain_fma<float>(L, n, x, y, w, z);
+    return finish();
+}
+
+}  // extern "C\"

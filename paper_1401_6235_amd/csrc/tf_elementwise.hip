@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kEwBlock) void ew_vec_kernel(int64_t n, const T *x0
                                                         const T *y0, const T *y1, T *z0, T *z1) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
-    constexpr bool HAS_Y = OP != OP_SQRT;
+    constexpr bool HAS_Y = !op_unary(OP);
     const int64_t nvec = n / W;
     for (int64_t grp = (int64_t)blockIdx.x * TF_EW_CHUNK; grp * kEwBlock * UNROLL < nvec;
          grp += (int64_t)gridDim.x * TF_EW_CHUNK)
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kEwBlock) void ew_vec_kernel(int64_t n, const T *x0
 template <typename T, int OP, bool XT, bool YT>
 __global__ __launch_bounds__(kBlock) void ew_scalar_kernel(int64_t n, const T *x0, const T *x1,
                                                            const T *y0, const T *y1, T *z0, T *z1) {
-    constexpr bool HAS_Y = OP != OP_SQRT;
+    constexpr bool HAS_Y = !op_unary(OP);
     const int64_t step = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += step) {
         const Pair<T> z = apply<T, OP, XT, YT>(x0[i], XT ? x1[i] : T(0), HAS_Y ? y0[i] : T(0),
@@ -108,8 +108,8 @@ template <typename T, int OP, bool XT, bool YT>
 static void launch_ew(const Launch &L, int64_t n, const T *x0, const T *x1, const T *y0, const T *y1,
                       T *z0, T *z1) {
     constexpr int UNROLL = sizeof(T) == 8 ? TF_EW_UNROLL_F64
-                           : OP == OP_SQRT ? TF_EW_UNROLL_F32_UNARY
-                                           : TF_EW_UNROLL_F32;
+                           : op_unary(OP) ? TF_EW_UNROLL_F32_UNARY
+                                          : TF_EW_UNROLL_F32;
     if (L.aligned) {
         const int64_t nvec = n / Vec<T>::N;
         const unsigned g = grid_for(nvec, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
@@ -132,6 +132,12 @@ static void dispatch_ew(const Launch &L, int64_t n, const T *x0, const T *x1, co
     else launch_ew<T, OP, false, false>(L, n, x0, x1, y0, y1, z0, z1);
 }
 
+template <typename T, int OP>
+static void dispatch_unary(const Launch &L, int64_t n, const T *x0, const T *x1, T *z0, T *z1) {
+    if (x1) launch_ew<T, OP, true, false>(L, n, x0, x1, nullptr, nullptr, z0, z1);
+    else launch_ew<T, OP, false, false>(L, n, x0, nullptr, nullptr, nullptr, z0, z1);
+}
+
 template <typename T>
 void run_elementwise(const Launch &L, int op, int64_t n, const void *x0, const void *x1,
                      const void *y0, const void *y1, void *z0, void *z1) {
@@ -142,9 +148,19 @@ void run_elementwise(const Launch &L, int op, int64_t n, const void *x0, const v
     case OP_SUB: dispatch_ew<T, OP_SUB>(L, n, a0, a1, b0, b1, c0, c1); break;
     case OP_MUL: dispatch_ew<T, OP_MUL>(L, n, a0, a1, b0, b1, c0, c1); break;
     case OP_DIV: dispatch_ew<T, OP_DIV>(L, n, a0, a1, b0, b1, c0, c1); break;
-    default:
-        if (a1) launch_ew<T, OP_SQRT, true, false>(L, n, a0, a1, nullptr, nullptr, c0, c1);
-        else launch_ew<T, OP_SQRT, false, false>(L, n, a0, nullptr, nullptr, nullptr, c0, c1);
+    case OP_SQRT: dispatch_unary<T, OP_SQRT>(L, n, a0, a1, c0, c1); break;
+    case OP_MUL_P: dispatch_ew<T, OP_MUL_P>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_DIV_P: dispatch_ew<T, OP_DIV_P>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_SQRT_P: dispatch_unary<T, OP_SQRT_P>(L, n, a0, a1, c0, c1); break;
+    case OP_RENORM + OP_ADD: dispatch_ew<T, OP_RENORM + OP_ADD>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_RENORM + OP_SUB: dispatch_ew<T, OP_RENORM + OP_SUB>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_RENORM + OP_MUL_P: dispatch_ew<T, OP_RENORM + OP_MUL_P>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_RENORM + OP_DIV_P: dispatch_ew<T, OP_RENORM + OP_DIV_P>(L, n, a0, a1, b0, b1, c0, c1); break;
+    case OP_RENORM + OP_SQRT_P: dispatch_unary<T, OP_RENORM + OP_SQRT_P>(L, n, a0, a1, c0, c1); break;
+    case OP_FAST_TWO_SUM:
+        launch_ew<T, OP_FAST_TWO_SUM, true, false>(L, n, a0, a1, nullptr, nullptr, c0, c1);
+        break;
+    default: break;  // codes are checked by the caller
     }
 }
 template void run_elementwise<double>(const Launch &, int, int64_t, const void *, const void *,

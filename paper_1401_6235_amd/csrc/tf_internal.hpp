@@ -40,6 +40,27 @@ void run_horner(const Launch &L, int64_t n, int degree, const void *c, const voi
 template <typename T>
 void run_plain_horner(const Launch &L, int64_t n, int degree, const void *c, const void *x, void *z);
 
+int chain_code(int op, int mode);
+template <typename T>
+void run_chain(const Launch &L, int code, int64_t n, int64_t reps, const void *x0, const void *x1,
+               const void *y0, const void *y1, void *z0, void *z1);
+template <typename T>
+void run_plain_chain(const Launch &L, int op, int64_t n, int64_t reps, const void *x, const void *y, void *z);
+template <typename T>
+void run_trsv(const Launch &L, int64_t nsys, int m, const void *U0, const void *U1, const void *f0,
+              const void *f1, void *x0, void *x1);
+template <typename T>
+void run_plain_trsv(const Launch &L, int64_t nsys, int m, const void *U, const void *f, void *x);
+template <typename T>
+void run_quadratic(const Launch &L, int64_t n, const void *const *in, void *const *out);
+template <typename T>
+void run_plain_quadratic(const Launch &L, int64_t n, const void *a, const void *b, const void *c, void *r,
+                         void *s);
+template <typename T>
+void run_fma(const Launch &L, int64_t n, const void *const *in, void *z0, void *z1);
+template <typename T>
+void run_plain_fma(const Launch &L, int64_t n, const void *x, const void *y, const void *w, void *z);
+
 // Leaf kinds of the reduction tree.
 enum Leaf {
     LEAF_SUM_D = 0,   // dotted values; Two-Sum at level 1

@@ -54,13 +54,52 @@ __device__ __forceinline__ void vstore(T *p, int64_t vi, typename Vec<T>::type v
 #endif
 }
 
-enum Op { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4 };
+// Operation codes.  0..4 are the twofold operations; 5..7 the coupled
+// multiply, divide and square root (MPF1, DPF1, RPF1; coupled add and
+// subtract are ATF1 / STF1 themselves); OP_RENORM added to any of these
+// passes the result through Fast Two-Sum (Dekker mode); OP_FAST_TWO_SUM
+// renormalises the twofold x alone.
+enum Op {
+    OP_ADD = 0,
+    OP_SUB = 1,
+    OP_MUL = 2,
+    OP_DIV = 3,
+    OP_SQRT = 4,
+    OP_MUL_P = 5,
+    OP_DIV_P = 6,
+    OP_SQRT_P = 7,
+    OP_RENORM = 8,
+    OP_FAST_TWO_SUM = 16,
+};
+
+// Operations with one operand.
+constexpr bool op_unary(int op) {
+    return op == OP_FAST_TWO_SUM || (op & 7) == OP_SQRT || (op & 7) == OP_SQRT_P;
+}
 
 // One element of a binary operation; XT / YT: operand is twofold (else
-// dotted).  For OP_SQRT only x is used.
+// dotted).  For unary operations only x is used.
 template <typename T, int OP, bool XT, bool YT>
 __device__ __forceinline__ Pair<T> apply(T x0, T x1, T y0, T y1) {
-    if constexpr (OP == OP_ADD) {
+    if constexpr (OP == OP_FAST_TWO_SUM) {
+        return fast_two_sum(x0, x1);
+    } else if constexpr ((OP & OP_RENORM) != 0) {
+        const Pair<T> z = apply<T, OP & 7, XT, YT>(x0, x1, y0, y1);
+        return fast_two_sum(z.hi, z.lo);
+    } else if constexpr (OP == OP_MUL_P) {
+        if constexpr (XT && YT) return mul_pp(x0, x1, y0, y1);
+        else if constexpr (XT) return mul_td(x0, x1, y0);
+        else if constexpr (YT) return mul_dt(x0, y0, y1);
+        else return mul_dd(x0, y0);
+    } else if constexpr (OP == OP_DIV_P) {
+        if constexpr (XT && YT) return div_pp(x0, x1, y0, y1);
+        else if constexpr (XT) return div_td(x0, x1, y0);
+        else if constexpr (YT) return div_pp(x0, T(0), y0, y1);
+        else return div_dd(x0, y0);
+    } else if constexpr (OP == OP_SQRT_P) {
+        if constexpr (XT) return sqrt_p(x0, x1);
+        else return sqrt_d(x0);
+    } else if constexpr (OP == OP_ADD) {
         if constexpr (XT && YT) return add_tt(x0, x1, y0, y1);
         else if constexpr (XT) return add_td(x0, x1, y0);
         else if constexpr (YT) return add_dt(x0, y0, y1);

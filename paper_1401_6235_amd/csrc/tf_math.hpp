@@ -171,4 +171,57 @@ __device__ __forceinline__ Pair<T> sqrt_d(T x0) {
     return {q, h / (T(2) * q)};
 }
 
+// ---- coupled ("p") algorithms and renormalisation ----------------------------
+// For coupled operands (|x1| at most half an ulp of x0) the p-algorithms
+// drop what is negligible; Fast Two-Sum renormalises a result (Dekker mode).
+
+// Fast Two-Sum, Algorithm 1.1: exact when |a| >= |b|.
+template <typename T>
+__device__ __forceinline__ Pair<T> fast_two_sum(T a, T b) {
+    const T s = a + b;
+    const T bb = s - a;            // b as it survives inside s
+    return {s, b - bb};
+}
+// MPF1: MTF1 without x1 y1; z1 = e00 (+) (p01 (+) p10).
+template <typename T>
+__device__ __forceinline__ Pair<T> mul_pp(T x0, T x1, T y0, T y1) {
+    const Pair<T> p = two_prod(x0, y0);
+    const T cross = x0 * y1 + x1 * y0;
+    return {p.hi, p.lo + cross};
+}
+// DPF1: DTF1 dividing by y0 alone; z1 = (r0 (+) r1) (/) y0.
+template <typename T>
+__device__ __forceinline__ Pair<T> div_pp(T x0, T x1, T y0, T y1) {
+    const T q = x0 / y0;
+    const T r0 = fma_rn(-q, y0, x0);
+    const T r1 = fma_rn(-q, y1, x1);
+    return {q, (r0 + r1) / y0};
+}
+// RPF1: one Newton step from sqrt(x0), z1 = (x1 (+) (x0 - z0^2)) (/) (2 z0).
+template <typename T>
+__device__ __forceinline__ Pair<T> sqrt_p(T x0, T x1) {
+    const T q = sqrt_rn(x0);
+    const T h = fma_rn(-q, q, x0);
+    return {q, (x1 + h) / (T(2) * q)};
+}
+
+// ---- twofold fma: z = x y + w (an extension of the paper's operations) --------
+// z0 = fma(x0, y0, w0).  The error of that fma is rounded with Boldo and
+// Muller's ErrFma steps (the exact error is r2 + r3 with r2 its rounded
+// value): (u1, u2) = TP(x0, y0); (a1, a2) = TS(w0, u2); (b1, b2) = TS(u1, a1);
+// r2 = ((b1 - z0) + b2) + a2.  The low-part terms follow MTF1, then w1.
+template <typename T, bool XT, bool YT, bool WT>
+__device__ __forceinline__ Pair<T> fma_t(T x0, T x1, T y0, T y1, T w0, T w1) {
+    const T z0 = fma_rn(x0, y0, w0);
+    const Pair<T> u = two_prod(x0, y0);
+    const Pair<T> a = two_sum(w0, u.lo);
+    const Pair<T> b = two_sum(u.hi, a.hi);
+    T t = ((b.hi - z0) + b.lo) + a.lo;
+    if constexpr (XT && YT) t = (t + x1 * y1) + (x0 * y1 + x1 * y0);
+    else if constexpr (XT) t = t + x1 * y0;
+    else if constexpr (YT) t = t + x0 * y1;
+    if constexpr (WT) t = t + w1;
+    return {z0, t};
+}
+
 }  // namespace tf

@@ -26,6 +26,7 @@ SOURCE = os.path.join(_HERE, "illdot.c")
 
 # Stream keys (first element of the spawn key).
 _K_X, _K_Y, _K_AXPY, _K_HORNER, _K_DOT = 1, 2, 3, 4, 5
+_K_CHAIN, _K_TRSV, _K_QUAD, _K_FMA = 7, 8, 9, 10
 
 F64 = np.dtype(np.float64)
 F32 = np.dtype(np.float32)
@@ -160,6 +161,141 @@ def horner_case(n: int, seed: int = 0, dtype=F64, degree: int = 8):
     x032 = x0.astype(np.float32)
     u32 = u.astype(np.float32) * np.float32(2.0 ** -24)
     return {"c": c32, "x0": x032, "x1": x032 * u32}
+
+
+# ---------------------------------------------------------------------------
+# Chains, batched applications, fma
+# ---------------------------------------------------------------------------
+
+def _low_part(x0, g, dtype):
+    """x1 = x0 * (u 2^-p), u uniform in [-1, 1) (n doubles from g)."""
+    u = g.uniform(-1.0, 1.0, x0.size)
+    if np.dtype(dtype) == F64:
+        return x0 * (u * 2.0 ** -53)
+    return x0 * (u.astype(np.float32) * np.float32(2.0 ** -24))
+
+
+def chain_case(op: str, n: int, seed: int = 0, dtype=F64):
+    """Start values x and operands y for chains of many steps that stay in
+    range: x a twofold operand with exponents in [-4, 4] (|x| for sqrt);
+    for add / sub, y a twofold operand with exponents in [-16, -8]; for mul /
+    div, y0 = 1 + v 2^-12 with v uniform in [-1, 1) (a few thousand steps
+    change the value by a factor of at most e or so), y1 = y0 u 2^-p.
+
+    Draw order: x from stream (seed, 7, 1); y from stream (seed, 7, 2): for
+    mul / div n doubles v then n doubles u.
+    """
+    dtype = np.dtype(dtype)
+    x0, x1 = twofold_operand(n, seed, _K_CHAIN, dtype, -4, 4)
+    out = {"x0": x0, "x1": x1}
+    if op == "sqrt":
+        neg = np.signbit(x0)
+        out["x0"] = np.abs(x0)
+        out["x1"] = np.where(neg, -x1, x1)
+        return out
+    if op in ("add", "sub"):
+        y0, y1 = twofold_operand(n, seed + 7919, _K_CHAIN, dtype, -16, -8)
+    else:
+        g = rng(seed, _K_CHAIN, 2)
+        y0 = (1.0 + g.uniform(-1.0, 1.0, n) * 2.0 ** -12).astype(dtype)
+        y1 = _low_part(y0, g, dtype)
+    out.update(y0=np.ascontiguousarray(y0), y1=np.ascontiguousarray(y1))
+    return out
+
+
+def trsv_case(m: int, nsys: int, seed: int = 0, dtype=F64, kind: str = "jordan"):
+    """Upper-triangular systems, interleaved (entry (i, j) of system k at
+    [(i*m + j)*nsys + k], f_i at [i*nsys + k]); the strictly lower part is 0.
+
+    kind "jordan" (the paper's test matrix): diagonal lambda_k with |lambda|
+    log-uniform in [2^-min(10, 40/m), 1] and a random sign, 1 on the first
+    superdiagonal; for binary32 lambda is drawn as a double and split into
+    its float and the float of the remainder, as the paper initialises it.
+    kind "dense": entries above the diagonal uniform in [-1, 1), diagonal
+    +-(1 + uniform[0, 1)), low parts x0 u 2^-p.  f is a twofold operand with
+    exponents in [-2, 2].  Growth stays below 2^64 in both kinds.
+
+    Draw order in stream (seed, 8, m): jordan: nsys doubles for log2|lambda|,
+    nsys sign integers; dense: m*m*nsys doubles for the entries, m*nsys
+    doubles for the diagonal magnitudes, m*nsys sign integers, m*m*nsys
+    doubles u for the low parts.
+    """
+    dtype = np.dtype(dtype)
+    g = rng(seed, _K_TRSV, m)
+    U0 = np.zeros((m, m, nsys), np.float64)
+    U1 = np.zeros((m, m, nsys), np.float64)
+    if kind == "jordan":
+        lo = -min(10.0, 40.0 / m)
+        lam = np.exp2(g.uniform(lo, 0.0, nsys)) * np.where(g.integers(0, 2, nsys) == 1, -1.0, 1.0)
+        lam0 = lam.astype(dtype)
+        lam1 = (lam - lam0.astype(np.float64)).astype(dtype)
+        for i in range(m):
+            U0[i, i] = lam0
+            U1[i, i] = lam1
+            if i + 1 < m:
+                U0[i, i + 1] = 1.0
+        U0, U1 = U0.astype(dtype), U1.astype(dtype)
+    elif kind == "dense":
+        vals = g.uniform(-1.0, 1.0, (m, m, nsys))
+        diag = 1.0 + g.uniform(0.0, 1.0, (m, nsys))
+        sgn = np.where(g.integers(0, 2, (m, nsys)) == 1, -1.0, 1.0)
+        upper = np.triu(np.ones((m, m), bool), 1)[:, :, None]
+        U0 = np.where(upper, vals, 0.0)
+        for i in range(m):
+            U0[i, i] = diag[i] * sgn[i]
+        U0 = U0.astype(dtype)
+        U1 = np.where(U0 != 0, _low_part(U0.reshape(-1), g, dtype).reshape(U0.shape), 0).astype(dtype)
+    else:
+        raise ValueError(kind)
+    f0, f1 = twofold_operand(m * nsys, seed, _K_TRSV + 100 * m, dtype, -2, 2)
+    return {"m": m, "U0": np.ascontiguousarray(U0.reshape(-1)), "U1": np.ascontiguousarray(U1.reshape(-1)),
+            "f0": f0, "f1": f1}
+
+
+def quadratic_case(n: int, seed: int = 0, dtype=F64):
+    """Coefficients of a x^2 + b x + c with twofold parts: a, b twofold
+    operands with exponents in [-2, 2]; c in three equal-odds classes:
+    random (either sign of the discriminant), small (c = b^2 / (4a) times
+    2^-k, k uniform in [20, 40]: the cancellation of the paper's c = 1e-8
+    example) and near a double root (c = b^2 / (4a) (1 + v 2^-20), v
+    uniform in [-1, 1)).  c1 = c0 u 2^-p.
+
+    Draw order: a, b from streams (seed, 9, 1), (seed, 9, 2); stream
+    (seed, 9, 3): n class integers, n doubles r (random class, c = r in
+    [-4, 4)), n integers k, n doubles v, n doubles u.
+    """
+    dtype = np.dtype(dtype)
+    a0, a1 = twofold_operand(n, seed, _K_QUAD, dtype, -2, 2)
+    b0, b1 = twofold_operand(n, seed + 7919, _K_QUAD, dtype, -2, 2)
+    g = rng(seed, _K_QUAD, 3)
+    cls = g.integers(0, 3, n)
+    r = g.uniform(-4.0, 4.0, n)
+    k = g.integers(20, 41, n)
+    v = g.uniform(-1.0, 1.0, n)
+    crit = b0.astype(np.float64) ** 2 / (4.0 * a0.astype(np.float64))
+    c = np.where(cls == 0, r, np.where(cls == 1, crit * np.exp2(-k.astype(np.float64)), crit * (1 + v * 2.0 ** -20)))
+    c0 = c.astype(dtype)
+    c1 = _low_part(c0, g, dtype)
+    return {"a0": a0, "a1": a1, "b0": b0, "b1": b1, "c0": c0, "c1": np.ascontiguousarray(c1)}
+
+
+def fma_case(n: int, seed: int = 0, dtype=F64):
+    """x, y, w twofold operands with exponents in [-10, 10]; for one third of
+    the elements w0 = -(x0 y0)(1 + v 2^-20), rounded (v uniform in [-1, 1)),
+    so that the fma cancels.
+
+    Draw order: x, y, w from streams (seed, 10, 1/2/3); stream (seed, 10, 4):
+    n class integers then n doubles v.
+    """
+    dtype = np.dtype(dtype)
+    x0, x1 = twofold_operand(n, seed, _K_FMA, dtype, -10, 10)
+    y0, y1 = twofold_operand(n, seed + 7919, _K_FMA, dtype, -10, 10)
+    w0, w1 = twofold_operand(n, seed + 15838, _K_FMA, dtype, -10, 10)
+    g = rng(seed, _K_FMA, 4)
+    near = g.integers(0, 3, n) == 0
+    v = g.uniform(-1.0, 1.0, n)
+    w0 = np.where(near, -(x0.astype(np.float64) * y0.astype(np.float64)) * (1 + v * 2.0 ** -20), w0).astype(dtype)
+    return {"x0": x0, "x1": x1, "y0": y0, "y1": y1, "w0": np.ascontiguousarray(w0), "w1": w1}
 
 
 # ---------------------------------------------------------------------------

@@ -23,7 +23,8 @@ def declared_functions():
 def test_header_declares_the_api():
     names = declared_functions()
     for required in ("tf_add", "tf_sub", "tf_mul", "tf_div", "tf_sqrt", "tf_axpy", "tf_horner",
-                     "tf_sum", "tf_dot"):
+                     "tf_sum", "tf_dot", "tf_coupled", "tf_renorm", "tf_chain", "tf_plain_chain",
+                     "tf_trsv_upper", "tf_quadratic", "tf_fma"):
         assert required in names
 
 
@@ -50,3 +51,14 @@ def test_host_only_calls():
     # tuning knobs validate their values
     assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(3)) == -1
     assert lib.tf_config(99, ctypes.c_int64(1)) == -1
+    # the chain, coupled and application calls validate op, mode and sizes
+    i64 = ctypes.c_int64
+    assert lib.tf_coupled(tf.TF_F64, 5, 0, i64(10), None, None, None, None, None, None, None) == -1
+    assert lib.tf_chain(tf.TF_F64, 0, 3, i64(10), i64(1), None, None, None, None, None, None, None) == -1
+    assert lib.tf_chain(tf.TF_F64, 0, 0, i64(10), i64(-1), None, None, None, None, None, None, None) == -1
+    assert lib.tf_chain(tf.TF_F32, 2, 2, i64(0), i64(5), None, None, None, None, None, None, None) == 0
+    assert lib.tf_trsv_upper(tf.TF_F64, i64(4), 0, None, None, None, None, None, None, None) == -1
+    assert lib.tf_trsv_upper(tf.TF_F64, i64(4), tf.TF_MAX_TRSV + 1, None, None, None, None, None, None,
+                             None) == -1
+    assert lib.tf_quadratic(tf.TF_F64, i64(3), *([None] * 10), None) == -1
+    assert lib.tf_fma(tf.TF_F32, i64(0), *([None] * 8), None) == 0
