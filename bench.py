@@ -333,7 +333,8 @@ STEP_FLOPS = {
     ("add", "coupled", True): 8, ("sub", "coupled", True): 8, ("mul", "coupled", True): 7,
     ("div", "coupled", True): 7, ("sqrt", "coupled", True): 6,
 }
-TRSV_NSYS, TRSV_M = 1 << 16, 16
+TRSV_NSYS, TRSV_M = 1 << 20, 16           # dense 16 x 16 systems
+JORDAN_NSYS, JORDAN_M = 1 << 24, 3         # the paper's 3 x 3 Jordan blocks
 QUAD_N = 1 << 24
 FMA_N = 1 << 26
 
@@ -393,24 +394,29 @@ def in_register_run(torch, tf, W, steps=3, warmup=1):
 
 
 def applications_run(torch, tf, W, steps=3, warmup=1):
-    """Batched back-substitution (dense upper-triangular, m = 16, 2^16
-    systems), both quadratic roots (n = 2^24) and the twofold fma
+    """Batched back-substitution (the paper's 3 x 3 Jordan blocks, 2^24
+    systems; dense 16 x 16, 2^20 systems), both quadratic roots (n = 2^24)
+    and the twofold fma
     (n = 2^26): time, HBM rate of the algorithmic bytes, slowdown against
     the plain kernels."""
     import numpy as np
     out = {}
     for dt, tag, es in ((np.float64, "f64", 8), (np.float32, "f32", 4)):
-        m, ns = TRSV_M, TRSV_NSYS
-        c = W.trsv_case(m, ns, seed=0, dtype=dt, kind="dense")
-        g = {k: torch.from_numpy(v).cuda() for k, v in c.items() if k != "m"}
-        x0, x1 = torch.empty_like(g["f0"]), torch.empty_like(g["f0"])
-        ms = time_call(torch, lambda: tf.tf_trsv_upper(m, g["U0"], g["U1"], g["f0"], g["f1"], x0, x1), steps, warmup)
-        pms = time_call(torch, lambda: tf.tf_plain_trsv_upper(m, g["U0"], g["f0"], x0), steps, warmup)
-        alg = (m * (m + 1) // 2 * 2 + 4 * m) * es * ns  # upper U twofold, f and x twofold
-        out["trsv_" + tag] = {"nsys": ns, "m": m, "ms": round(ms, 4), "plain_ms": round(pms, 4),
-                              "gb_s": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
-                              "slowdown": round(ms / pms, 3)}
-        del g, x0, x1
+        for key, kind, m, ns in (("jordan3", "jordan", JORDAN_M, JORDAN_NSYS), ("trsv16", "dense", TRSV_M, TRSV_NSYS)):
+            c = W.trsv_case(m, ns, seed=0, dtype=dt, kind=kind)
+            g = {k: torch.from_numpy(v).cuda() for k, v in c.items() if k != "m"}
+            del c
+            x0, x1 = torch.empty_like(g["f0"]), torch.empty_like(g["f0"])
+            ms = time_call(torch, lambda: tf.tf_trsv_upper(m, g["U0"], g["U1"], g["f0"], g["f1"], x0, x1),
+                           steps, warmup)
+            pms = time_call(torch, lambda: tf.tf_plain_trsv_upper(m, g["U0"], g["f0"], x0), steps, warmup)
+            alg = (m * (m + 1) // 2 * 2 + 4 * m) * es * ns  # upper U twofold, f and x twofold
+            palg = (m * (m + 1) // 2 + 2 * m) * es * ns
+            out["%s_%s" % (key, tag)] = {
+                "nsys": ns, "m": m, "ms": round(ms, 4), "plain_ms": round(pms, 4),
+                "gb_s": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                "plain_gb_s": round(palg / pms / 1e6, 1), "slowdown": round(ms / pms, 3)}
+            del g, x0, x1
         q = W.quadratic_case(QUAD_N, seed=0, dtype=dt)
         g = {k: torch.from_numpy(v).cuda() for k, v in q.items()}
         outs = tuple(torch.empty_like(g["a0"]) for _ in range(4))
@@ -442,6 +448,9 @@ def applications_run(torch, tf, W, steps=3, warmup=1):
 
 # rocprofv3 kernel names -> bench keys
 _OPS = {"0": "add", "1": "sub", "2": "mul", "3": "div", "4": "sqrt"}
+_CHAIN = {0: "add", 1: "sub", 2: "mul", 3: "div", 4: "sqrt", 5: "mul_coupled", 6: "div_coupled",
+          7: "sqrt_coupled", 8: "add_dekker", 9: "sub_dekker", 13: "mul_dekker", 14: "div_dekker",
+          15: "sqrt_dekker"}
 
 
 def bench_key(name: str):
@@ -450,7 +459,7 @@ def bench_key(name: str):
     if t is None:
         return None
     m = re.search(r"ew_vec_kernel<\w+, (\d), true, (true|false)", name)
-    if m:
+    if m and m.group(1) in _OPS:
         return "%s_%s" % (_OPS[m.group(1)], t)
     if "axpy_vec_kernel" in name and "true, true" in name:
         return "axpy_" + t
@@ -461,12 +470,69 @@ def bench_key(name: str):
         return ("sum_" if m.group(1) == "1" else "dot_") + t
     if re.search(r"plain_vec_kernel<\w+, 99,", name):
         return "vmem_" + t
+    m = re.search(r"\bchain_kernel<\w+, (\d+), (true|false)", name)
+    if m and "plain_chain" not in name:
+        code, yt = int(m.group(1)), m.group(2) == "true"
+        op = _CHAIN.get(code)
+        if op is None:
+            return None
+        return "chain_%s%s_%s" % (op, "" if yt or "sqrt" in op else "_dotted_y", t)
+    m = re.search(r"plain_chain_kernel<\w+, (\d),", name)
+    if m:
+        return "plain_chain_%s_%s" % (_OPS[m.group(1)], t)
+    m = re.search(r"\btrsv_fixed_kernel<\w+, (\d+), true, true>", name)
+    if m and "plain" not in name:
+        return {"3": "jordan3_", "16": "trsv16_"}.get(m.group(1), "trsv%s_" % m.group(1)) + t
+    m = re.search(r"plain_trsv_fixed_kernel<\w+, (\d+)>", name)
+    if m:
+        return "plain_" + {"3": "jordan3_", "16": "trsv16_"}.get(m.group(1), "trsv%s_" % m.group(1)) + t
+    if "quadratic_vec_kernel" in name:
+        return "quadratic_" + t
+    if "plain_quadratic_kernel" in name:
+        return "plain_quadratic_" + t
+    if "fma_vec_kernel" in name and "true, true, true" in name:
+        return "fma_" + t
+    if "plain_fma_kernel" in name:
+        return "plain_fma_" + t
     return None
 
 
+def alg_bytes(key: str):
+    """Algorithmic HBM bytes of one launch of a benchmarked kernel."""
+    base, t = key.rsplit("_", 1)
+    es = 8 if t == "f64" else 4
+    plain = base.startswith("plain_")
+    b = base[6:] if plain else base
+    if b == "vmem":
+        return 3 * es * N_STREAM
+    if b in KERNELS:
+        n = N_REDUCE if b in ("sum", "dot") else N_STREAM
+        return KERNELS[b][0] * es * n
+    if b in ("jordan3", "trsv16"):
+        m, ns = (JORDAN_M, JORDAN_NSYS) if b == "jordan3" else (TRSV_M, TRSV_NSYS)
+        words = (m * (m + 1) // 2 + 2 * m) if plain else (m * (m + 1) // 2 * 2 + 4 * m)
+        return words * es * ns
+    if b == "quadratic":
+        return (5 if plain else 10) * es * QUAD_N
+    if b == "fma":
+        return (4 if plain else 8) * es * FMA_N
+    return None
+
+
+_GROUPS = [
+    ("hot_path_step_n2e28", "the benchmark step (n = 2^28 elementwise, 2^26 reductions)",
+     lambda k: k.rsplit("_", 1)[0] in KERNELS or k.startswith("vmem")),
+    ("chains_n2e21_reps256", "the in-register chains (n = 2^21, 256 steps)",
+     lambda k: k.startswith("chain_") or k.startswith("plain_chain_")),
+    ("applications_jordan3_trsv16_quadratic_fma",
+     "the batched applications (3x3 Jordan 2^24, 16x16 dense 2^20, quadratic 2^24, fma 2^26)",
+     lambda k: k.rsplit("_", 1)[0].replace("plain_", "") in ("jordan3", "trsv16", "quadratic", "fma")),
+]
+
+
 def summarize_profiles(prof_dir: str, command: str):
-    """Write profiles/hot_path_step_n2e28_{kernel_trace,counters}.txt and
-    profiles/traffic.json from a rocprofv3 run of this benchmark: kernel
+    """Write profiles/<group>_kernel_trace.txt, <group>_counters.txt and
+    profiles/traffic.json from rocprofv3 runs of this benchmark: kernel
     statistics (--kernel-trace --stats) in prof_dir/trace, FETCH_SIZE and
     WRITE_SIZE (--pmc, one counter per run) in prof_dir/fetch and
     prof_dir/write.  FETCH_SIZE / WRITE_SIZE are scaled by the factor that
@@ -477,13 +543,16 @@ def summarize_profiles(prof_dir: str, command: str):
     os.makedirs(out_dir, exist_ok=True)
     stats = glob.glob(os.path.join(prof_dir, "trace", "*kernel_stats.csv"))[0]
     rows = list(csv.DictReader(open(stats)))
-    lines = ["# rocprofv3 kernel statistics of the benchmark step (n = 2^28 elementwise, 2^26 reductions)",
-             "# command: " + command, "# source hash: " + kernel_source_hash(),
-             "%-14s %6s %12s  %s" % ("bench_key", "calls", "avg_us", "kernel")]
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        k = bench_key(r["Name"]) or "-"
-        lines.append("%-14s %6s %12.2f  %s" % (k, r["Calls"], float(r["AverageNs"]) / 1e3, r["Name"][:110]))
-    open(os.path.join(out_dir, "hot_path_step_n2e28_kernel_trace.txt"), "w").write("\n".join(lines) + "\n")
+    src = kernel_source_hash()
+    for fname, what, member in _GROUPS:
+        lines = ["# rocprofv3 kernel statistics of " + what,
+                 "# command: " + command, "# source hash: " + src,
+                 "%-28s %6s %12s  %s" % ("bench_key", "calls", "avg_us", "kernel")]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            k = bench_key(r["Name"])
+            if k and member(k):
+                lines.append("%-28s %6s %12.2f  %s" % (k, r["Calls"], float(r["AverageNs"]) / 1e3, r["Name"][:110]))
+        open(os.path.join(out_dir, fname + "_kernel_trace.txt"), "w").write("\n".join(lines) + "\n")
 
     def counters(which):
         f = glob.glob(os.path.join(prof_dir, which, "*counter_collection.csv"))[0]
@@ -495,7 +564,7 @@ def summarize_profiles(prof_dir: str, command: str):
         return {k: sum(v) / len(v) for k, v in acc.items()}
 
     fetch, write = counters("fetch"), counters("write")
-    traffic = {"source_hash": kernel_source_hash(), "command": command, "kernels": {}}
+    traffic = {"source_hash": src, "command": command, "kernels": {}}
     factors = {}
     for t, es in (("f64", 8), ("f32", 4)):
         n = N_STREAM
@@ -503,26 +572,28 @@ def summarize_profiles(prof_dir: str, command: str):
         w = (n * es) / (write["vmem_" + t] * 1024)
         factors[t] = (f, w)
     traffic["scale"] = {t: {"fetch": round(f, 4), "write": round(w, 4)} for t, (f, w) in factors.items()}
-    lines = ["# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per",
-             "# dispatch, one counter per run), scaled so the copy kernel reads and writes its known bytes",
-             "# command: " + command, "# source hash: " + kernel_source_hash(),
-             "# scale factors (fetch, write): " + json.dumps(traffic["scale"]),
-             "%-12s %14s %14s %16s %16s %8s" % ("bench_key", "FETCH_KiB", "WRITE_KiB", "traffic_B",
-                                                "algorithmic_B", "ratio")]
-    for k in sorted(set(fetch) & set(write)):
-        base, t = k.rsplit("_", 1)
-        es = 8 if t == "f64" else 4
-        f, w = factors[t]
-        b = fetch[k] * 1024 * f + write[k] * 1024 * w
-        n = N_REDUCE if base in ("sum", "dot") else N_STREAM
-        words = 3 if base == "vmem" else KERNELS[base][0]
-        alg = words * es * n
-        traffic["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(b),
-                                 "algorithmic_bytes": alg}
-        lines.append("%-12s %14.0f %14.0f %16.0f %16d %8.4f" % (k, fetch[k], write[k], b, alg, b / alg))
-    open(os.path.join(out_dir, "hot_path_step_n2e28_counters.txt"), "w").write("\n".join(lines) + "\n")
+    for fname, what, member in _GROUPS:
+        keys = [k for k in sorted(set(fetch) & set(write)) if member(k) and alg_bytes(k)]
+        if not keys or fname.startswith("chains"):
+            continue
+        lines = ["# HBM traffic per launch of " + what + ", from rocprofv3 --pmc FETCH_SIZE and",
+                 "# --pmc WRITE_SIZE (KiB per dispatch, one counter per run), scaled so the copy kernel",
+                 "# reads and writes its known bytes",
+                 "# command: " + command, "# source hash: " + src,
+                 "# scale factors (fetch, write): " + json.dumps(traffic["scale"]),
+                 "%-24s %14s %14s %16s %16s %8s" % ("bench_key", "FETCH_KiB", "WRITE_KiB", "traffic_B",
+                                                    "algorithmic_B", "ratio")]
+        for k in keys:
+            t = k.rsplit("_", 1)[1]
+            f, w = factors[t]
+            b = fetch[k] * 1024 * f + write[k] * 1024 * w
+            alg = alg_bytes(k)
+            traffic["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(b),
+                                     "algorithmic_bytes": alg}
+            lines.append("%-24s %14.0f %14.0f %16.0f %16d %8.4f" % (k, fetch[k], write[k], b, alg, b / alg))
+        open(os.path.join(out_dir, fname + "_counters.txt"), "w").write("\n".join(lines) + "\n")
+        print("\n".join(lines))
     json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
-    print("\n".join(lines))
 
 
 def main():

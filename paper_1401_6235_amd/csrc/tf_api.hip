@@ -322,7 +322,7 @@ int tf_quadratic(int dtype, int64_t n, const void *a0, const void *a1, const voi
     TF_CHECK(a0 && a1 && b0 && b1 && c0 && c1 && r0 && r1 && s0 && s1);
     const void *in[6] = {a0, a1, b0, b1, c0, c1};
     void *out[4] = {r0, r1, s0, s1};
-    const Launch L = make_launch(stream, {});
+    const Launch L = make_launch(stream, {a0, a1, b0, b1, c0, c1, r0, r1, s0, s1});
     if (dtype == TF_F64) run_quadratic<double>(L, n, in, out);
     else run_quadratic<float>(L, n, in, out);
     return finish();

@@ -4,9 +4,11 @@
 //
 //  * Back-substitution for upper-triangular m x m systems (the Jordan-block
 //    solve is the bidiagonal case).  Systems are interleaved in memory, so
-//    one index runs over systems and every load of a wave is coalesced; the
-//    solution entries a thread has already produced are read back from the
-//    output, where they are still cached.  Bound by reading the matrices.
+//    one index runs over systems and every load of a wave is coalesced.  For
+//    m <= 16 the order is a template constant and the solution stays in
+//    registers; larger orders read the entries a thread has already
+//    produced back from the output, where they are still cached.  Bound by
+//    reading the matrices.
 //  * Both roots of a quadratic by the school formula, NaN flowing through a
 //    negative discriminant.  Elementwise, bound by HBM.
 //  * z = x y + w with a twofold result.  Elementwise, bound by HBM.
@@ -37,6 +39,83 @@ __global__ __launch_bounds__(kBlock) void trsv_kernel(int64_t nsys, int m, const
     }
 }
 
+// Orders up to kTrsvFixed: m is a compile-time constant, every loop is
+// unrolled and the solution stays in registers, so all loads of a row are
+// issued together instead of one dependent iteration at a time.
+constexpr int kTrsvFixed = 16;
+
+template <typename T, int M, bool UT, bool FT>
+__global__ __launch_bounds__(kBlock) void trsv_fixed_kernel(int64_t nsys, const T *U0, const T *U1, const T *f0,
+                                                            const T *f1, T *x0, T *x1) {
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nsys; k += step) {
+        T r0[M], r1[M];
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+            Pair<T> s{f0[(int64_t)i * nsys + k], FT ? f1[(int64_t)i * nsys + k] : T(0)};
+#pragma unroll
+            for (int j = i + 1; j < M; ++j) {
+                const int64_t a = (int64_t)(i * M + j) * nsys + k;
+                const Pair<T> p = UT ? mul_tt(U0[a], U1[a], r0[j], r1[j]) : mul_dt(U0[a], r0[j], r1[j]);
+                s = sub_tt(s.hi, s.lo, p.hi, p.lo);
+            }
+            const int64_t d = (int64_t)(i * M + i) * nsys + k;
+            const Pair<T> x = UT ? div_tt(s.hi, s.lo, U0[d], U1[d]) : div_td(s.hi, s.lo, U0[d]);
+            r0[i] = x.hi;
+            r1[i] = x.lo;
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            x0[(int64_t)i * nsys + k] = r0[i];
+            x1[(int64_t)i * nsys + k] = r1[i];
+        }
+    }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kBlock) void plain_trsv_fixed_kernel(int64_t nsys, const T *U, const T *f, T *x) {
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nsys; k += step) {
+        T r[M];
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+            T s = f[(int64_t)i * nsys + k];
+#pragma unroll
+            for (int j = i + 1; j < M; ++j) s = s - U[(int64_t)(i * M + j) * nsys + k] * r[j];
+            r[i] = s / U[(int64_t)(i * M + i) * nsys + k];
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) x[(int64_t)i * nsys + k] = r[i];
+    }
+}
+
+template <typename T, int M>
+static void launch_trsv_fixed(const Launch &L, int64_t nsys, const T *a0, const T *a1, const T *b0, const T *b1,
+                              T *c0, T *c1) {
+    const dim3 g(grid_for(nsys, kBlock, 0)), b(kBlock);
+    if (a1 && b1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, true, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else if (a1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, true, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else if (b1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, false, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else hipLaunchKernelGGL((trsv_fixed_kernel<T, M, false, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+}
+
+template <typename T, int M = 1>
+static bool dispatch_trsv_fixed(const Launch &L, int m, int64_t nsys, const T *a0, const T *a1, const T *b0,
+                                const T *b1, T *c0, T *c1, const T *pu, const T *pf, T *px, bool plain) {
+    if constexpr (M > kTrsvFixed) {
+        return false;
+    } else {
+        if (m != M)
+            return dispatch_trsv_fixed<T, M + 1>(L, m, nsys, a0, a1, b0, b1, c0, c1, pu, pf, px, plain);
+        if (plain)
+            hipLaunchKernelGGL((plain_trsv_fixed_kernel<T, M>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0,
+                               L.stream, nsys, pu, pf, px);
+        else
+            launch_trsv_fixed<T, M>(L, nsys, a0, a1, b0, b1, c0, c1);
+        return true;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void plain_trsv_kernel(int64_t nsys, int m, const T *U, const T *f, T *x) {
     const int64_t step = (int64_t)gridDim.x * kBlock;
@@ -55,6 +134,7 @@ void run_trsv(const Launch &L, int64_t nsys, int m, const void *U0, const void *
     const unsigned g = grid_for(nsys, kBlock, 0);
     const T *a0 = (const T *)U0, *a1 = (const T *)U1, *b0 = (const T *)f0, *b1 = (const T *)f1;
     T *c0 = (T *)x0, *c1 = (T *)x1;
+    if (dispatch_trsv_fixed<T>(L, m, nsys, a0, a1, b0, b1, c0, c1, nullptr, nullptr, nullptr, false)) return;
     if (U1 && f1)
         hipLaunchKernelGGL((trsv_kernel<T, true, true>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0, a1, b0,
                            b1, c0, c1);
@@ -75,6 +155,9 @@ template void run_trsv<float>(const Launch &, int64_t, int, const void *, const 
 
 template <typename T>
 void run_plain_trsv(const Launch &L, int64_t nsys, int m, const void *U, const void *f, void *x) {
+    if (dispatch_trsv_fixed<T>(L, m, nsys, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (const T *)U,
+                               (const T *)f, (T *)x, true))
+        return;
     hipLaunchKernelGGL((plain_trsv_kernel<T>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0, L.stream, nsys,
                        m, (const T *)U, (const T *)f, (T *)x);
 }
@@ -126,11 +209,57 @@ __global__ __launch_bounds__(kBlock) void plain_quadratic_kernel(int64_t n, cons
     }
 }
 
+// 16-byte vectors of every array, one per thread; the ragged tail by block 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void quadratic_vec_kernel(int64_t n, const T *a0, const T *a1, const T *b0,
+                                                               const T *b1, const T *c0, const T *c1, T *r0,
+                                                               T *r1, T *s0, T *s1) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::N;
+    const int64_t nvec = n / W;
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nvec; i += step) {
+        const V pa0 = vload(a0, i), pa1 = vload(a1, i), pb0 = vload(b0, i), pb1 = vload(b1, i);
+        const V pc0 = vload(c0, i), pc1 = vload(c1, i);
+        V qr0, qr1, qs0, qs1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            Pair<T> r, s;
+            quadratic_one(pa0[k], pa1[k], pb0[k], pb1[k], pc0[k], pc1[k], r, s);
+            qr0[k] = r.hi;
+            qr1[k] = r.lo;
+            qs0[k] = s.hi;
+            qs1[k] = s.lo;
+        }
+        vstore(r0, i, qr0);
+        vstore(r1, i, qr1);
+        vstore(s0, i, qs0);
+        vstore(s1, i, qs1);
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nvec * W + threadIdx.x;
+        if (i < n) {
+            Pair<T> r, s;
+            quadratic_one(a0[i], a1[i], b0[i], b1[i], c0[i], c1[i], r, s);
+            r0[i] = r.hi;
+            r1[i] = r.lo;
+            s0[i] = s.hi;
+            s1[i] = s.lo;
+        }
+    }
+}
+
 template <typename T>
 void run_quadratic(const Launch &L, int64_t n, const void *const *in, void *const *out) {
-    hipLaunchKernelGGL((quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
-                       (const T *)in[0], (const T *)in[1], (const T *)in[2], (const T *)in[3], (const T *)in[4],
-                       (const T *)in[5], (T *)out[0], (T *)out[1], (T *)out[2], (T *)out[3]);
+    const T *a0 = (const T *)in[0], *a1 = (const T *)in[1], *b0 = (const T *)in[2], *b1 = (const T *)in[3];
+    const T *c0 = (const T *)in[4], *c1 = (const T *)in[5];
+    T *r0 = (T *)out[0], *r1 = (T *)out[1], *s0 = (T *)out[2], *s1 = (T *)out[3];
+    if (L.aligned)
+        hipLaunchKernelGGL((quadratic_vec_kernel<T>), dim3(grid_for(n / Vec<T>::N, kBlock, L.cap)), dim3(kBlock), 0,
+                           L.stream, n, a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
+    else
+        hipLaunchKernelGGL((quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
+                           a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
 }
 template void run_quadratic<double>(const Launch &, int64_t, const void *const *, void *const *);
 template void run_quadratic<float>(const Launch &, int64_t, const void *const *, void *const *);

@@ -20,10 +20,10 @@
 // Steps per loop iteration (the step count is a run-time value; a
 // remainder loop takes the rest).
 #ifndef TF_CHAIN_UNROLL
-#define TF_CHAIN_UNROLL 1
+#define TF_CHAIN_UNROLL 4
 #endif
 #ifndef TF_PLAIN_CHAIN_UNROLL
-#define TF_PLAIN_CHAIN_UNROLL 1
+#define TF_PLAIN_CHAIN_UNROLL 4
 #endif
 
 namespace tf {

@@ -30,7 +30,7 @@ def _poison_lower(U, m, nsys):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("kind", ["jordan", "dense"])
-@pytest.mark.parametrize("m", [1, 2, 3, 8, 17, 64])
+@pytest.mark.parametrize("m", [1, 2, 3, 8, 16, 17, 64])
 def test_trsv(m, kind, dtype):
     for nsys in (1, 255, 1000):
         c = W.trsv_case(m, nsys, seed=m + nsys, dtype=dtype, kind=kind)
@@ -97,6 +97,21 @@ def test_quadratic_paper_rows():
             assert_bits(to_np(g), w, "paper row")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_quadratic_misaligned(dtype):
+    torch = torch_cuda()
+    n = 100003
+    c = W.quadratic_case(n + 1, seed=12, dtype=dtype)
+    keys = ("a0", "a1", "b0", "b1", "c0", "c1")
+    step("quadratic misaligned %s" % np.dtype(dtype))
+    views = [to_gpu(c[k])[1:] for k in keys]
+    outs = tuple(torch.empty(n + 1, dtype=views[0].dtype, device="cuda")[1:] for _ in range(4))
+    tf.tf_quadratic(*views, out=outs)
+    want = oracle.quadratic(*[c[k][1:] for k in keys])
+    for g, w in zip(outs, want):
+        assert_bits(to_np(g), w, "misaligned quadratic")
+
+
 FORMS = [(x, y, w) for x in (True, False) for y in (True, False) for w in (True, False)]
 
 
@@ -132,7 +147,8 @@ def test_fma_misaligned(dtype):
     assert_bits(to_np(z1), want[1], "z1")
 
 
-TRSV_NSYS, TRSV_M = 1 << 16, 16
+TRSV_NSYS, TRSV_M = 1 << 20, 16
+JORDAN_NSYS, JORDAN_M = 1 << 24, 3
 QUAD_N = 1 << 24
 FMA_N = 1 << 26
 
@@ -154,7 +170,19 @@ def test_benchmark_sizes_sampled(dtype):
     want = oracle.trsv_upper(m, U0, U1, f0, f1)
     assert_bits(to_np(got[0]).reshape(m, TRSV_NSYS)[:, ks].reshape(-1), want[0], "x0")
     assert_bits(to_np(got[1]).reshape(m, TRSV_NSYS)[:, ks].reshape(-1), want[1], "x1")
-    del got
+    del got, c
+
+    m, ns = JORDAN_M, JORDAN_NSYS
+    c = W.trsv_case(m, ns, seed=0, dtype=dtype, kind="jordan")
+    step("bench jordan %s nsys=%d m=%d" % (np.dtype(dtype), ns, m))
+    got = tf.tf_trsv_upper(m, to_gpu(c["U0"]), to_gpu(c["U1"]), to_gpu(c["f0"]), to_gpu(c["f1"]))
+    ks = np.sort(g.choice(ns, 4096, replace=False))
+    sub = [c[k].reshape(m, m, ns)[:, :, ks].reshape(-1) for k in ("U0", "U1")]
+    fs = [c[k].reshape(m, ns)[:, ks].reshape(-1) for k in ("f0", "f1")]
+    want = oracle.trsv_upper(m, sub[0], sub[1], fs[0], fs[1])
+    assert_bits(to_np(got[0]).reshape(m, ns)[:, ks].reshape(-1), want[0], "jordan x0")
+    assert_bits(to_np(got[1]).reshape(m, ns)[:, ks].reshape(-1), want[1], "jordan x1")
+    del got, c
 
     q = W.quadratic_case(QUAD_N, seed=0, dtype=dtype)
     keys = ("a0", "a1", "b0", "b1", "c0", "c1")
