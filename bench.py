@@ -319,7 +319,7 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
 # ---------------------------------------------------------------------------
 
 CHAIN_N = 1 << 21
-CHAIN_REPS = 256
+CHAIN_REPS = 2048
 FP_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector FP64 / FP32, published
 # Algorithmic floating-point operations of one chain step, counting each
 # + - * / sqrt as one and each fma as two (the convention of the peaks).
@@ -522,7 +522,7 @@ def alg_bytes(key: str):
 _GROUPS = [
     ("hot_path_step_n2e28", "the benchmark step (n = 2^28 elementwise, 2^26 reductions)",
      lambda k: k.rsplit("_", 1)[0] in KERNELS or k.startswith("vmem")),
-    ("chains_n2e21_reps256", "the in-register chains (n = 2^21, 256 steps)",
+    ("chains_n2e21_reps2048", "the in-register chains (n = 2^21, 2048 steps)",
      lambda k: k.startswith("chain_") or k.startswith("plain_chain_")),
     ("applications_jordan3_trsv16_quadratic_fma",
      "the batched applications (3x3 Jordan 2^24, 16x16 dense 2^20, quadratic 2^24, fma 2^26)",

@@ -73,21 +73,62 @@ __device__ __forceinline__ void load4(const T *p, int64_t first, int64_t n, bool
 #define TF_RED_HALVES 1
 #endif
 
+// Exchange with lane ^ D.  With TF_RED_DPP, xor 1 and 2 are DPP quad
+// permutes (no LDS), xor 4, 8 and 16 ds_swizzle in bit-mask mode (no
+// address computation), xor 32 a ds_bpermute; otherwise every distance is
+// a ds_bpermute (__shfl_xor).  The value moved is the same either way.
+#ifndef TF_RED_DPP
+#define TF_RED_DPP 1
+#endif
+
+template <int D>
+__device__ __forceinline__ int lane_xor_u32(int x) {
+#if TF_RED_DPP
+    if constexpr (D == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    else if constexpr (D == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    else if constexpr (D < 32) return __builtin_amdgcn_ds_swizzle(x, 0x1F | (D << 10));
+    else return __shfl_xor(x, D);
+#else
+    return __shfl_xor(x, D);
+#endif
+}
+
+template <int D, typename T>
+__device__ __forceinline__ T lane_xor(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const long long b = __double_as_longlong(v);
+        const int lo = lane_xor_u32<D>((int)(b & 0xffffffffll));
+        const int hi = lane_xor_u32<D>((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __int_as_float(lane_xor_u32<D>(__float_as_int(v)));
+    }
+}
+
+// One butterfly step at distance D: every lane ends with the node joining
+// its group of 2D lanes; the lower group is the left child, so both lanes of
+// a pair evaluate the node in the same order and get the same bits.
+template <int D, typename T, bool PLAIN>
+__device__ __forceinline__ Pair<T> butterfly_step(Pair<T> v, int lane) {
+    Pair<T> o;
+    o.hi = lane_xor<D>(v.hi);
+    o.lo = PLAIN ? T(0) : lane_xor<D>(v.lo);
+    const bool left = (lane & D) == 0;
+    const Pair<T> l{left ? v.hi : o.hi, left ? v.lo : o.lo};
+    const Pair<T> r{left ? o.hi : v.hi, left ? o.lo : v.lo};
+    return node<T, PLAIN>(l, r);
+}
+
 // Butterfly over the 64 lanes: after step d (1, 2, .., 32) every lane holds
-// the node joining its group of 2d lanes; the lower group is the left child.
+// the node joining its group of 2d lanes.
 template <typename T, bool PLAIN>
 __device__ __forceinline__ Pair<T> butterfly(Pair<T> v, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        Pair<T> o;
-        o.hi = __shfl_xor(v.hi, d);
-        o.lo = PLAIN ? T(0) : __shfl_xor(v.lo, d);
-        const bool left = (lane & d) == 0;
-        const Pair<T> l{left ? v.hi : o.hi, left ? v.lo : o.lo};
-        const Pair<T> r{left ? o.hi : v.hi, left ? o.lo : v.lo};
-        v = node<T, PLAIN>(l, r);
-    }
-    return v;
+    v = butterfly_step<1, T, PLAIN>(v, lane);
+    v = butterfly_step<2, T, PLAIN>(v, lane);
+    v = butterfly_step<4, T, PLAIN>(v, lane);
+    v = butterfly_step<8, T, PLAIN>(v, lane);
+    v = butterfly_step<16, T, PLAIN>(v, lane);
+    return butterfly_step<32, T, PLAIN>(v, lane);
 }
 
 // Two consecutive values starting at `first` (even); beyond n read as +0.
@@ -188,15 +229,12 @@ __device__ __forceinline__ int ilog2(int64_t v) { return 63 - __clzll(v); }
 // them.  Lanes at or beyond m pair among themselves and are not used.
 template <typename T, bool PLAIN>
 __device__ __forceinline__ Pair<T> butterfly_m(Pair<T> v, int lane, int m) {
-    for (int d = 1; d < m; d <<= 1) {
-        Pair<T> o;
-        o.hi = __shfl_xor(v.hi, d);
-        o.lo = PLAIN ? T(0) : __shfl_xor(v.lo, d);
-        const bool left = (lane & d) == 0;
-        const Pair<T> l{left ? v.hi : o.hi, left ? v.lo : o.lo};
-        const Pair<T> r{left ? o.hi : v.hi, left ? o.lo : v.lo};
-        v = node<T, PLAIN>(l, r);
-    }
+    if (m > 1) v = butterfly_step<1, T, PLAIN>(v, lane);
+    if (m > 2) v = butterfly_step<2, T, PLAIN>(v, lane);
+    if (m > 4) v = butterfly_step<4, T, PLAIN>(v, lane);
+    if (m > 8) v = butterfly_step<8, T, PLAIN>(v, lane);
+    if (m > 16) v = butterfly_step<16, T, PLAIN>(v, lane);
+    if (m > 32) v = butterfly_step<32, T, PLAIN>(v, lane);
     return v;
 }
 

@@ -138,16 +138,16 @@ def test_clock_accumulator(hours, dtype):
 
 
 CHAIN_N = 1 << 21
-CHAIN_REPS = 256
+CHAIN_REPS = 2048
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("op", OPS)
 def test_benchmark_chain_sampled(op, dtype):
-    """The chain workload the benchmark times (n = 2^21, 256 steps), with
-    8192 sampled elements recomputed by the oracle."""
+    """The chain workload the benchmark times (n = 2^21, 2048 steps), with
+    2048 sampled elements recomputed by the oracle."""
     c = W.chain_case(op, CHAIN_N, seed=0, dtype=dtype)
-    idx = np.sort(np.random.default_rng(5).choice(CHAIN_N, 8192, replace=False))
+    idx = np.sort(np.random.default_rng(5).choice(CHAIN_N, 2048, replace=False))
     for mode in MODES:
         step("bench chain %s %s %s" % (op, mode, np.dtype(dtype)))
         got = tf.tf_chain(op, mode, CHAIN_REPS, to_gpu(c["x0"]), to_gpu(c["x1"]), to_gpu(c.get("y0")),
