@@ -1,13 +1,19 @@
-// The fixed pairwise reduction tree, device side: one 256-leaf tile per
-// wave and a binary counter for aligned groups of tiles.  Used by the
-// reduction kernels and by the serving kernel, so both evaluate the same
-// tree bit for bit.
+// The fixed pairwise reduction tree, device side.  Used by the reduction
+// kernels and by the serving kernel, so both evaluate the same tree bit for
+// bit.
 //
-// One wave reduces one tile: lane l holds leaves 4l .. 4l+3 (one 16-byte
-// load for binary32, two for binary64), forms tree levels 1-2 in registers
-// and levels 3-8 with a butterfly over the lanes (xor 1..32); both lanes of
-// a pair evaluate the node with the same left/right order, so all 64 lanes
-// end with identical bits.
+// Two mappings of 256-leaf tiles onto a wave, chosen by the number of tiles
+// a wave reduces:
+//  * tile pairs (two or more tiles per wave): a wave takes two adjacent
+//    tiles at once, transposes them through LDS so that each lane holds 8
+//    consecutive leaves, forms levels 1-3 in registers and levels 4-8 by a
+//    butterfly over 32 lanes;
+//  * single tiles: lane l holds leaves 4l .. 4l+3 (or two leaves of each
+//    half of the tile), levels 1-2 in registers, the rest by a butterfly
+//    over the 64 lanes.
+// In every butterfly both lanes of a pair evaluate the node with the same
+// left/right order, so all lanes end with identical bits; a wave then keeps
+// tile t's value in lane t and joins its tiles with one more butterfly.
 #pragma once
 
 #include "tf_internal.hpp"
@@ -22,6 +28,7 @@ struct LeafTraits {
     static constexpr bool has_x1 = LEAF == LEAF_SUM_T || LEAF == LEAF_DOT_TT || LEAF == LEAF_DOT_TD;
     static constexpr bool has_y0 = LEAF >= LEAF_DOT_DD && LEAF != LEAF_PSUM;
     static constexpr bool has_y1 = LEAF == LEAF_DOT_TT || LEAF == LEAF_DOT_DT;
+    static constexpr int arrays = 1 + has_x1 + has_y0 + has_y1;
 };
 
 // A tree node: ATF1 of the left and right child, or the plain sum.
@@ -224,6 +231,134 @@ __device__ __forceinline__ Pair<T> tile_value(int64_t tile, int64_t n, bool alig
 
 __device__ __forceinline__ int ilog2(int64_t v) { return 63 - __clzll(v); }
 
+// ---- tile pairs: 8 consecutive leaves per lane --------------------------------
+//
+// One wave reduces two adjacent tiles (512 leaves) at once.  Each array is
+// loaded with contiguous 16-byte vectors (lane l, vector k: leaves
+// W (64 k + l) ..), passed through a wave-private LDS region and read back
+// so that lane l holds leaves 8l .. 8l+7: tree levels 1-3 are formed in
+// registers, levels 4-8 by a butterfly over 32 lanes (DPP / swizzle only),
+// leaving the first tile's value in lanes 0-31 and the second's in lanes
+// 32-63.  The LDS region has one spare vector after every lane's group, so
+// the transposed reads are spread over the banks.
+#ifndef TF_RED_PAIRS
+#define TF_RED_PAIRS 1
+#endif
+#ifndef TF_RED_LDS_PAD
+#define TF_RED_LDS_PAD 1
+#endif
+#ifndef TF_RED_PAIR_ARRAYS
+#define TF_RED_PAIR_ARRAYS 2
+#endif
+
+template <typename T>
+struct PairLayout {
+    using V = typename Vec<T>::type;
+    static constexpr int W = Vec<T>::N;
+    static constexpr int VPL = 8 / W;      // vectors per lane per array
+    static constexpr int NV = 64 * VPL;    // vectors per array for 512 leaves
+    static constexpr int SLOTS = TF_RED_LDS_PAD ? NV + NV / VPL : NV;
+    __device__ static int slot(int v) { return TF_RED_LDS_PAD ? v + v / VPL : v; }
+};
+
+// One LDS region per kernel, shared by every instantiation (4 waves, sized
+// for binary64, the larger layout).
+constexpr int kPairLdsBytes = 4 * PairLayout<double>::SLOTS * 16;
+__device__ __forceinline__ void *pair_lds_base() {
+    __shared__ __attribute__((aligned(16))) unsigned char buf[kPairLdsBytes];
+    return buf;
+}
+
+template <typename T>
+struct PairData {
+    typename Vec<T>::type r[4][PairLayout<T>::VPL];  // x0, x1, y0, y1 as loaded
+};
+
+template <typename T, int LEAF>
+__device__ __forceinline__ void pair_load(PairData<T> &D, int64_t tile, int64_t n, bool aligned, const T *x0,
+                                          const T *x1, const T *y0, const T *y1) {
+    using Tr = LeafTraits<LEAF>;
+    using L = PairLayout<T>;
+    const int lane = threadIdx.x & 63;
+    const int64_t first = tile * kTile;  // leaf index of the pair's first leaf
+    const bool vec = aligned && first + 2 * kTile <= n;
+    const T *src[4] = {x0, x1, y0, y1};
+    const bool has[4] = {true, Tr::has_x1, Tr::has_y0, Tr::has_y1};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (!has[a]) continue;
+#pragma unroll
+        for (int k = 0; k < L::VPL; ++k) {
+            const int64_t v = first / L::W + k * 64 + lane;  // vector index
+            if (vec) {
+                D.r[a][k] = vload(src[a], v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < L::W; ++e) {
+                    const int64_t i = v * L::W + e;
+                    D.r[a][k][e] = i < n ? src[a][i] : T(0);
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+    }
+}
+
+// Values of the two tiles of a loaded pair: lanes 0-31 hold the first tile's,
+// lanes 32-63 the second's.  `lds` is this wave's region of L::SLOTS vectors.
+template <typename T, int LEAF>
+__device__ __forceinline__ Pair<T> pair_reduce(const PairData<T> &D, typename Vec<T>::type *lds) {
+    using Tr = LeafTraits<LEAF>;
+    using L = PairLayout<T>;
+    const int lane = threadIdx.x & 63;
+    const bool has[4] = {true, Tr::has_x1, Tr::has_y0, Tr::has_y1};
+    T lv[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (!has[a]) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) lv[a][i] = T(0);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < L::VPL; ++k) lds[L::slot(k * 64 + lane)] = D.r[a][k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int j = 0; j < L::VPL; ++j) {
+            const typename Vec<T>::type v = lds[L::slot(lane * L::VPL + j)];
+#pragma unroll
+            for (int e = 0; e < L::W; ++e) lv[a][j * L::W + e] = v[e];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    Pair<T> l1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) l1[i] = level1<T, LEAF>(lv[0], lv[1], lv[2], lv[3], 2 * i);
+    const Pair<T> l2a = node<T, Tr::plain>(l1[0], l1[1]);
+    const Pair<T> l2b = node<T, Tr::plain>(l1[2], l1[3]);
+    Pair<T> v = node<T, Tr::plain>(l2a, l2b);
+    v = butterfly_step<1, T, Tr::plain>(v, lane);
+    v = butterfly_step<2, T, Tr::plain>(v, lane);
+    v = butterfly_step<4, T, Tr::plain>(v, lane);
+    v = butterfly_step<8, T, Tr::plain>(v, lane);
+    return butterfly_step<16, T, Tr::plain>(v, lane);
+}
+
 // Butterfly over the first m lanes (m a power of two, at most 64): the
 // adjacent-pairing tree of the values held by lanes 0 .. m-1, left in each of
 // them.  Lanes at or beyond m pair among themselves and are not used.
@@ -267,6 +402,35 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
     const int per_wave = per_block >= 4 ? per_block / 4 : 1;
     const int waves = per_block / per_wave;
     Pair<T> mine{T(0), T(0)};
+#if TF_RED_PAIRS
+    // Tile pairs pay off where the tree dominates the per-leaf work: leaves
+    // read from one or two arrays (sums, dot of plain vectors).  Leaves with
+    // three or four input arrays (twofold products) are already near the
+    // read bandwidth on single tiles, and the extra transposes cost more
+    // than the saved tree levels (measured on MI355X).
+    if (LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS && per_wave >= 2) {  // per_wave: a power of two
+        typename Vec<T>::type *lds =
+            reinterpret_cast<typename Vec<T>::type *>(pair_lds_base()) + wave * PairLayout<T>::SLOTS;
+        const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
+        PairData<T> cur, nxt;
+        if (t0 < tiles) pair_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
+        for (int p = 0; 2 * p < per_wave; ++p) {
+            const int64_t tile = t0 + 2 * p;
+            if (2 * p + 2 < per_wave && tile + 2 < tiles)
+                pair_load<T, LEAF>(nxt, tile + 2, n, aligned, x0, x1, y0, y1);
+            if (tile < tiles) {
+                const Pair<T> v = pair_reduce<T, LEAF>(cur, lds);
+                const Pair<T> first{readlane_t(v.hi, 0), readlane_t(v.lo, 0)};
+                const Pair<T> second{readlane_t(v.hi, 32), readlane_t(v.lo, 32)};
+                if (lane == 2 * p) mine = first;
+                if (lane == 2 * p + 1 && tile + 1 < tiles) mine = second;
+            }
+            cur = nxt;
+        }
+        mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
+        return join_waves<T, PLAIN>(mine, waves);
+    }
+#endif
     if (wave < waves) {
         const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
         // software pipeline: the next tile's loads are in flight while the

@@ -201,3 +201,27 @@ def test_benchmark_sizes_sampled(dtype):
     want = oracle.fma(*[f[k][idx] for k in ("x0", "x1", "y0", "y1", "w0", "w1")])
     assert_bits(to_np(got[0])[idx], want[0], "fma z0")
     assert_bits(to_np(got[1])[idx], want[1], "fma z1")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_special_values_fma_and_quadratic(dtype):
+    """Specials in every position of the fma (all operand forms) and of the
+    quadratic's coefficients."""
+    from test_gpu_elementwise import special_values
+    v = special_values(dtype)
+    m = v.size
+    g = np.random.default_rng(4)
+    idx = g.integers(0, m, (6, 1 << 18))
+    x0, x1, y0, y1, w0, w1 = (v[i] for i in idx)
+    for xt, yt, wt in FORMS:
+        step("specials fma %s forms=%d%d%d" % (np.dtype(dtype), xt, yt, wt))
+        a1, b1, c1 = (x1 if xt else None), (y1 if yt else None), (w1 if wt else None)
+        want = oracle.fma(x0, a1, y0, b1, w0, c1)
+        got = tf.tf_fma(to_gpu(x0), to_gpu(a1), to_gpu(y0), to_gpu(b1), to_gpu(w0), to_gpu(c1))
+        assert_bits(to_np(got[0]), want[0], "fma z0")
+        assert_bits(to_np(got[1]), want[1], "fma z1")
+    step("specials quadratic %s" % np.dtype(dtype))
+    want = oracle.quadratic(x0, x1, y0, y1, w0, w1)
+    got = tf.tf_quadratic(*[to_gpu(a) for a in (x0, x1, y0, y1, w0, w1)])
+    for gg, w in zip(got, want):
+        assert_bits(to_np(gg), w, "quadratic")

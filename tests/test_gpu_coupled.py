@@ -156,3 +156,44 @@ def test_benchmark_chain_sampled(op, dtype):
         want = oracle.chain(op, mode, CHAIN_REPS, sub["x0"], sub["x1"], sub.get("y0"), sub.get("y1"))
         assert_bits(to_np(got[0])[idx], want[0], "z0")
         assert_bits(to_np(got[1])[idx], want[1], "z1")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_special_values_coupled_and_renorm(dtype):
+    """Signed zeros, infinities, NaN, subnormals and extremes in every
+    position of the coupled and Dekker operations and of Fast Two-Sum."""
+    from test_gpu_elementwise import special_values
+    v = special_values(dtype)
+    m = v.size
+    idx = np.indices((m, m, m, m)).reshape(4, -1)
+    c = dict(zip(("x0", "x1", "y0", "y1"), (v[i] for i in idx)))
+    step("specials coupled %s n=%d" % (np.dtype(dtype), c["x0"].size))
+    for op in OPS:
+        forms = [(True, False), (False, False)] if op == "sqrt" else [(1, 1), (1, 0), (0, 1), (0, 0)]
+        for renorm in (False, True):
+            for xt, yt in forms:
+                got, want = _coupled_both(op, c, xt, yt, renorm)
+                assert_bits(got[0], want[0], "%s z0 %d%d r%d" % (op, xt, yt, renorm))
+                assert_bits(got[1], want[1], "%s z1 %d%d r%d" % (op, xt, yt, renorm))
+    got = tf.tf_renorm(to_gpu(c["x0"]), to_gpu(c["x1"]))
+    want = oracle.renorm(c["x0"], c["x1"])
+    assert_bits(to_np(got[0]), want[0], "renorm s")
+    assert_bits(to_np(got[1]), want[1], "renorm t")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_special_values_chains(dtype):
+    """Specials as start values and operands of short chains (NaN and
+    infinities flow through every step as the oracle's do)."""
+    from test_gpu_elementwise import special_values
+    v = special_values(dtype)
+    m = v.size
+    idx = np.indices((m, m, m, m)).reshape(4, -1)
+    x0, x1, y0, y1 = (v[i] for i in idx)
+    for op in OPS:
+        for mode in MODES:
+            step("specials chain %s %s %s" % (op, mode, np.dtype(dtype)))
+            want = oracle.chain(op, mode, 5, x0, x1, y0, y1)
+            got = tf.tf_chain(op, mode, 5, to_gpu(x0), to_gpu(x1), to_gpu(y0), to_gpu(y1))
+            assert_bits(to_np(got[0]), want[0], "chain z0")
+            assert_bits(to_np(got[1]), want[1], "chain z1")
