@@ -290,7 +290,7 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
         return round(float(np.percentile(np.array(xs), 50)) * 1e6, 1)
 
     breakdown = {
-        "driver_late_us_p50": p50([r["t_submit"] - r["t_arrive"] for r in res]),
+        "submit_late_us_p50": p50([r["t_submit"] - r["t_arrive"] for r in res]),
         "admit_us_p50": p50([r["t_admit"] - r["t_submit"] for r in res]),
         "materialise_publish_us_p50": p50([r["t_publish"] - r["t_admit"] for r in res]),
         "device_and_completion_us_p50": p50([r["t_done"] - r["t_publish"] for r in res]),
@@ -594,6 +594,79 @@ def summarize_profiles(prof_dir: str, command: str):
         open(os.path.join(out_dir, fname + "_counters.txt"), "w").write("\n".join(lines) + "\n")
         print("\n".join(lines))
     json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
+    if os.path.isdir(os.path.join(prof_dir, "valu64")) and os.path.isdir(os.path.join(prof_dir, "valu32")):
+        summarize_valu(prof_dir, command, rows)
+
+
+VALU64 = "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 " \
+         "SQ_ACTIVE_INST_VALU SQ_INSTS_VALU GRBM_GUI_ACTIVE"
+VALU32 = "SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_TRANS_F32 " \
+         "SQ_THREAD_CYCLES_VALU GRBM_GUI_ACTIVE"
+
+
+def summarize_valu(prof_dir: str, command: str, trace_rows):
+    """profiles/<group>_valu.txt from two --pmc runs (VALU64, VALU32
+    counters) of the benchmark: executed FP64 / FP32 operations per launch
+    (each ADD / MUL / TRANS wave instruction is 64 operations, each FMA 128)
+    and their rate over the kernel's average traced duration against the
+    vector peaks (78.6 / 157.3 TFLOP/s); VALU wave instructions per CU per
+    cycle (SQ_INSTS_VALU over the counted run's cycles: GRBM_GUI_ACTIVE,
+    summed over the 8 XCDs, divided by 8) and the clock of that run (cycles
+    over its own dispatch duration)."""
+    import csv
+    import glob
+    dur = {}
+    for r in trace_rows:
+        k = bench_key(r["Name"])
+        if k:
+            dur[k] = float(r["AverageNs"]) * 1e-9
+
+    def per_kernel(which):
+        f = glob.glob(os.path.join(prof_dir, which, "*counter_collection.csv"))[0]
+        acc, span = {}, {}
+        for r in csv.DictReader(open(f)):
+            k = bench_key(r["Kernel_Name"])
+            if k:
+                acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                span.setdefault(k, {})[r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
+        out = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+        for k, d in span.items():
+            out[k]["_seconds"] = sum(d.values()) / len(d)
+        return out
+
+    c64, c32 = per_kernel("valu64"), per_kernel("valu32")
+    src = kernel_source_hash()
+    for fname, what, member in _GROUPS:
+        keys = [k for k in sorted(set(c64) & set(c32) & set(dur)) if member(k)]
+        if not keys:
+            continue
+        lines = ["# VALU work per launch of " + what + ", from rocprofv3 --pmc runs of",
+                 "# " + VALU64, "# and " + VALU32,
+                 "# (per dispatch; FP ops = 64 per ADD/MUL/TRANS wave instruction, 128 per FMA; TFLOP/s over the",
+                 "# traced average duration against the peaks 78.6 (FP64) / 157.3 (FP32); valu_ipc = SQ_INSTS_VALU",
+                 "# per CU per cycle, cycles = GRBM_GUI_ACTIVE / 8 XCDs; issue ceiling 1.0 for full-rate FP64",
+                 "# instructions (4 SIMDs x one wave instruction per 4 cycles) and 2.0 for FP32, which issues at",
+                 "# twice that rate (the FP32 chains reach 1.8); GHz = cycles / the counted dispatch's own",
+                 "# duration, an estimate that short dispatches overstate by a few percent)",
+                 "# command: " + command, "# source hash: " + src,
+                 "%-28s %10s %12s %8s %12s %8s %9s %6s" % ("bench_key", "avg_us", "fp64_TFLOP/s", "frac64",
+                                                        "fp32_TFLOP/s", "frac32", "valu_ipc", "GHz")]
+        for k in keys:
+            a, b = c64[k], c32[k]
+            t = dur[k]
+            f64 = 64 * (a.get("SQ_INSTS_VALU_ADD_F64", 0) + a.get("SQ_INSTS_VALU_MUL_F64", 0)
+                        + a.get("SQ_INSTS_VALU_TRANS_F64", 0) + 2 * a.get("SQ_INSTS_VALU_FMA_F64", 0))
+            f32 = 64 * (b.get("SQ_INSTS_VALU_ADD_F32", 0) + b.get("SQ_INSTS_VALU_MUL_F32", 0)
+                        + b.get("SQ_INSTS_VALU_TRANS_F32", 0) + 2 * b.get("SQ_INSTS_VALU_FMA_F32", 0))
+            cycles = a.get("GRBM_GUI_ACTIVE", 0) / 8
+            ipc = a.get("SQ_INSTS_VALU", 0) / (cycles * 256) if cycles else 0
+            ghz = cycles / a["_seconds"] / 1e9 if a.get("_seconds") else 0
+            lines.append("%-28s %10.1f %12.2f %8.4f %12.2f %8.4f %9.3f %6.2f" % (
+                k, t * 1e6, f64 / t / 1e12, f64 / t / 1e12 / FP_PEAK_TFLOPS["f64"], f32 / t / 1e12,
+                f32 / t / 1e12 / FP_PEAK_TFLOPS["f32"], ipc, ghz))
+        open(os.path.join(ROOT, "profiles", fname + "_valu.txt"), "w").write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+
 
 
 def main():

@@ -145,7 +145,7 @@ def run_stream(srv: "Server", times, jobs, keep=None, t0_delay: float = 0.05, ti
     """Submit jobs[k] at tfs_clock() time t0 + times[k] (busy-waiting on the
     clock, polling completions in between) and wait for all results.
     Returns (ids, {id: result}); arrival times are the scheduled ones, so
-    any lateness of this driver counts against the measured latency."""
+    any lateness of this submitting loop counts against the measured latency."""
     import time as _time
     t0 = tfs_clock() + t0_delay
     ids, results = [], {}
