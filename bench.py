@@ -8,10 +8,14 @@ synthetic inputs, binary64 and binary32:
     Horner, degree 8                                     n = 2^28
     sum (twofold leaves), dot (plain vectors)            n = 2^26, cond 1e16
 The same pass with the plain (non-twofold) kernels and the memory probe is
-timed right after, for the twofold/plain slowdown.  Then the serving stream
-runs (20,000 verification jobs at 2,000 jobs/s on the persistent kernel) and
-reports p50 / p99 latency, throughput and flag counts.  value = twofold
-elements per second over the step (input elements for the reductions).
+timed right after, for the twofold/plain slowdown.  Then, outside the step:
+the in-register chains (every operation, twofold / coupled / Dekker, against
+the plain chain: the paper's in-cache criterion), the batched applications
+and the fma, each against its plain kernel, and the paper's own slowdowns
+as context; then the serving stream (20,000 verification jobs at 2,000
+jobs/s on the persistent kernel) with p50 / p99 latency, throughput and
+flag counts.  value = twofold elements per second over the step (input
+elements for the reductions).
 
 Per-kernel durations come from HIP events on the launch stream around each
 kernel, averaged over the timed steps.  The roofline entry is for the
@@ -669,6 +673,26 @@ def summarize_valu(prof_dir: str, command: str, trace_rows):
 
 
 
+# The paper's own twofold/plain ratios (its Tables 1 and 2: Intel Core
+# i5-4200U, AVX2, binary64, both operands twofold; sub against vadd, as the
+# paper has no vsub): large arrays (DRAM) and small ones (L1).
+PAPER_SLOWDOWN_LARGE = {"add": 2.10, "sub": 2.17, "mul": 2.04, "div": 2.22, "sqrt": 3.41}
+PAPER_SLOWDOWN_SMALL = {"add": 6.48, "sub": 6.59, "mul": 3.95, "div": 2.23, "sqrt": 3.35}
+
+
+def paper_context(kernels, in_register):
+    """The paper's slowdowns beside ours (binary64): HBM-resident arrays
+    against its large arrays, in-register chains against its L1 arrays.
+    Context only: another machine and another memory system."""
+    ops = ("add", "sub", "mul", "div", "sqrt")
+    out = {"source": "the paper's Tables 1-2 (Intel Core i5-4200U, AVX2, binary64, twofold operands vs plain)",
+           "paper_large_arrays": PAPER_SLOWDOWN_LARGE, "paper_l1_arrays": PAPER_SLOWDOWN_SMALL,
+           "ours_hbm_n2e28": {op: kernels["%s_f64" % op]["slowdown"] for op in ops}}
+    if in_register:
+        out["ours_in_register"] = {op: in_register["ops"]["%s_f64" % op]["twofold"]["slowdown"] for op in ops}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -794,6 +818,7 @@ def main():
         result["in_register"] = in_register_run(torch, tf, W)
         log("batched applications and fma")
         result["applications"] = applications_run(torch, tf, W)
+    result["paper_context"] = paper_context(kernels, result.get("in_register"))
     if args.serve_jobs > 0:
         result["serving"] = serving_run(torch, W, jobs=args.serve_jobs)
     if not args.no_cpu_baseline:
