@@ -181,14 +181,22 @@ def traffic_for(kernel_key: str, src_hash: str):
 
 
 def cpu_baseline(W, seconds_target=15.0):
-    """The oracle (single-threaded scalar C) on a bounded sample of the
+    """The oracle (scalar C, loaded with ctypes) on a bounded sample of the
     step: every kernel of the step on n = 2^20 elements (2^20 leaves for
-    the reductions), binary64 and binary32."""
+    the reductions), binary64 and binary32, timed on one thread and then on
+    every host core.  The all-core run partitions each call into one
+    contiguous chunk per thread (independent elements; for sum and dot,
+    subtrees of the tree when the thread count is a power of two, the final
+    join of the per-thread results left out); ctypes releases the
+    interpreter lock, so the chunks run in parallel.  value is the all-core
+    rate."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import oracle
     n = 1 << 20
-    total_elems = 0
-    t_total = 0.0
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    jobs_by_type = []
     for dt in (np.float64, np.float32):
         c = W.elementwise("add", n, seed=0, dtype=dt)
         s = W.elementwise("sqrt", n, seed=0, dtype=dt)
@@ -196,30 +204,38 @@ def cpu_baseline(W, seconds_target=15.0):
         r = W.illdot_case(n, REDUCE_COND, seed=0, dtype=dt)
         hi, lo = W.product_split(r["x"], r["y"])
         a = W.axpy_case(1, dtype=dt)["a"]
-        jobs = [
-            lambda: oracle.add(c["x0"], c["x1"], c["y0"], c["y1"]),
-            lambda: oracle.sub(c["x0"], c["x1"], c["y0"], c["y1"]),
-            lambda: oracle.mul(c["x0"], c["x1"], c["y0"], c["y1"]),
-            lambda: oracle.div(c["x0"], c["x1"], c["y0"], c["y1"]),
-            lambda: oracle.sqrt(s["x0"], s["x1"]),
-            lambda: oracle.axpy(a, c["x0"], c["x1"], c["y0"], c["y1"]),
-            lambda: oracle.horner(h["c"], h["x0"], h["x1"]),
-            lambda: oracle.sum(hi, lo),
-            lambda: oracle.dot(r["x"], None, r["y"], None),
-        ]
-        reps = 0
-        t0 = time.perf_counter()
+        jobs_by_type.append([
+            lambda i, j, c=c: oracle.add(c["x0"][i:j], c["x1"][i:j], c["y0"][i:j], c["y1"][i:j]),
+            lambda i, j, c=c: oracle.sub(c["x0"][i:j], c["x1"][i:j], c["y0"][i:j], c["y1"][i:j]),
+            lambda i, j, c=c: oracle.mul(c["x0"][i:j], c["x1"][i:j], c["y0"][i:j], c["y1"][i:j]),
+            lambda i, j, c=c: oracle.div(c["x0"][i:j], c["x1"][i:j], c["y0"][i:j], c["y1"][i:j]),
+            lambda i, j, s=s: oracle.sqrt(s["x0"][i:j], s["x1"][i:j]),
+            lambda i, j, c=c, a=a: oracle.axpy(a, c["x0"][i:j], c["x1"][i:j], c["y0"][i:j], c["y1"][i:j]),
+            lambda i, j, h=h: oracle.horner(h["c"], h["x0"][i:j], h["x1"][i:j]),
+            lambda i, j, hi=hi, lo=lo: oracle.sum(hi[i:j], lo[i:j]),
+            lambda i, j, r=r: oracle.dot(r["x"][i:j], None, r["y"][i:j], None),
+        ])
+    jobs = [j for js in jobs_by_type for j in js]
+
+    def timed(run, budget):
+        reps, t0 = 0, time.perf_counter()
         while True:
-            for j in jobs:
-                j()
+            for job in jobs:
+                run(job)
             reps += 1
-            if time.perf_counter() - t0 > seconds_target / 2:
-                break
-        t_total += time.perf_counter() - t0
-        total_elems += reps * n * len(jobs)
-    return {"value": total_elems / t_total / 1e9, "unit": "Gelem/s", "cores": 1, "kind": "oracle",
+            if time.perf_counter() - t0 > budget:
+                return reps * n * len(jobs), time.perf_counter() - t0
+
+    e1, t1 = timed(lambda job: job(0, n), seconds_target)
+    chunk = n // cores
+    bounds = [(k * chunk, n if k == cores - 1 else (k + 1) * chunk) for k in range(cores)]
+    with ThreadPoolExecutor(cores) as pool:
+        ea, ta = timed(lambda job: list(pool.map(lambda b: job(*b), bounds)), seconds_target / 3)
+    return {"value": ea / ta / 1e9, "unit": "Gelem/s", "cores": cores, "kind": "oracle",
+            "value_1_thread": e1 / t1 / 1e9,
             "sample": "every kernel of the step (add, sub, mul, div, sqrt, axpy, horner-8, sum, dot), "
-                      "binary64 and binary32, on n = 2^20 elements each, single thread, %.1f s" % t_total}
+                      "binary64 and binary32, on n = 2^20 elements each: %.1f s on 1 thread, then %.1f s "
+                      "partitioned over %d threads" % (t1, ta, cores)}
 
 
 def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
@@ -673,6 +689,52 @@ def summarize_valu(prof_dir: str, command: str, trace_rows):
 
 
 
+CACHE_N = 1 << 20
+CACHE_LAUNCHES = 50
+
+
+def cache_resident_run(torch, tf, W, warmup=3):
+    """The paper's "medium" arrays (its L3 case): elementwise operations at
+    n = 2^20, whose operands (at most 48 MiB in binary64) stay in the 256 MB
+    Infinity Cache across back-to-back calls.  Time of CACHE_LAUNCHES calls
+    in a row between two HIP events, per call; twofold (both operands
+    twofold) against plain."""
+    import numpy as np
+    out = {"n": CACHE_N, "launches": CACHE_LAUNCHES, "ops": {}}
+    stream = torch.cuda.current_stream()
+    for dt, tag, es in ((np.float64, "f64", 8), (np.float32, "f32", 4)):
+        for op in ("add", "sub", "mul", "div", "sqrt"):
+            c = W.elementwise(op, CACHE_N, seed=0, dtype=dt)
+            g = {k: torch.from_numpy(v).cuda() for k, v in c.items()}
+            z0, z1 = torch.empty_like(g["x0"]), torch.empty_like(g["x0"])
+            if op == "sqrt":
+                two = lambda: tf.tf_sqrt(g["x0"], g["x1"], z0, z1)  # noqa: E731
+                one = lambda: tf.tf_plain_sqrt(g["x0"], z0)  # noqa: E731
+                words = (4, 2)
+            else:
+                two = lambda: getattr(tf, "tf_" + op)(g["x0"], g["x1"], g["y0"], g["y1"], z0, z1)  # noqa: E731
+                one = lambda: getattr(tf, "tf_plain_" + op)(g["x0"], g["y0"], z0)  # noqa: E731
+                words = (6, 3)
+            res = []
+            for fn in (two, one):
+                for _ in range(warmup):
+                    fn()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(CACHE_LAUNCHES):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                res.append(a.elapsed_time(b) / CACHE_LAUNCHES)
+            ms, pms = res
+            out["ops"]["%s_%s" % (op, tag)] = {
+                "ms": round(ms, 5), "gelem_s": round(CACHE_N / ms / 1e6, 1),
+                "gb_s": round(words[0] * es * CACHE_N / ms / 1e6, 1), "plain_ms": round(pms, 5),
+                "plain_gelem_s": round(CACHE_N / pms / 1e6, 1), "slowdown": round(ms / pms, 3)}
+            del g, z0, z1
+    return out
+
+
 # The paper's own twofold/plain ratios (its Tables 1 and 2: Intel Core
 # i5-4200U, AVX2, binary64, both operands twofold; sub against vadd, as the
 # paper has no vsub): large arrays (DRAM) and small ones (L1).
@@ -680,14 +742,21 @@ PAPER_SLOWDOWN_LARGE = {"add": 2.10, "sub": 2.17, "mul": 2.04, "div": 2.22, "sqr
 PAPER_SLOWDOWN_SMALL = {"add": 6.48, "sub": 6.59, "mul": 3.95, "div": 2.23, "sqrt": 3.35}
 
 
-def paper_context(kernels, in_register):
+PAPER_SLOWDOWN_MEDIUM = {"add": 2.04, "sub": 2.10, "mul": 2.00, "div": 2.23, "sqrt": 3.37}
+
+
+def paper_context(kernels, in_register, cache_resident=None):
     """The paper's slowdowns beside ours (binary64): HBM-resident arrays
-    against its large arrays, in-register chains against its L1 arrays.
-    Context only: another machine and another memory system."""
+    against its large arrays, cache-resident ones against its medium (L3)
+    arrays, in-register chains against its L1 arrays.  Context only:
+    another machine and another memory system."""
     ops = ("add", "sub", "mul", "div", "sqrt")
     out = {"source": "the paper's Tables 1-2 (Intel Core i5-4200U, AVX2, binary64, twofold operands vs plain)",
-           "paper_large_arrays": PAPER_SLOWDOWN_LARGE, "paper_l1_arrays": PAPER_SLOWDOWN_SMALL,
+           "paper_large_arrays": PAPER_SLOWDOWN_LARGE, "paper_medium_arrays": PAPER_SLOWDOWN_MEDIUM,
+           "paper_l1_arrays": PAPER_SLOWDOWN_SMALL,
            "ours_hbm_n2e28": {op: kernels["%s_f64" % op]["slowdown"] for op in ops}}
+    if cache_resident:
+        out["ours_cache_resident_n2e20"] = {op: cache_resident["ops"]["%s_f64" % op]["slowdown"] for op in ops}
     if in_register:
         out["ours_in_register"] = {op: in_register["ops"]["%s_f64" % op]["twofold"]["slowdown"] for op in ops}
     return out
@@ -764,6 +833,9 @@ def main():
         v = pper["vmem_" + tag]
         kernels["vmem_" + tag] = {"n": v["n"], "ms": round(v["ms_avg"], 4),
                                   "gb_s": round(v["n"] * 3 * es / v["ms_avg"] / 1e6, 1)}
+    for name in list(kernels):  # the HBM rate against the measured copy bandwidth too
+        if not name.startswith("vmem"):
+            kernels[name]["copy_frac"] = round(kernels[name]["gb_s"] / kernels["vmem_" + name.rsplit("_", 1)[1]]["gb_s"], 4)
 
     dom = max((k for k in kernels if not k.startswith("vmem")), key=lambda k: kernels[k]["ms"])
     base, tag = dom.rsplit("_", 1)
@@ -818,7 +890,10 @@ def main():
         result["in_register"] = in_register_run(torch, tf, W)
         log("batched applications and fma")
         result["applications"] = applications_run(torch, tf, W)
-    result["paper_context"] = paper_context(kernels, result.get("in_register"))
+    if not args.no_extra:
+        log("cache-resident elementwise (n = 2^20)")
+        result["cache_resident"] = cache_resident_run(torch, tf, W)
+    result["paper_context"] = paper_context(kernels, result.get("in_register"), result.get("cache_resident"))
     if args.serve_jobs > 0:
         result["serving"] = serving_run(torch, W, jobs=args.serve_jobs)
     if not args.no_cpu_baseline:
