@@ -220,15 +220,17 @@ def random_jobs(count, seed, max_log2=20):
 
 
 def test_mix_equals_alone():
+    """600 jobs submitted together overlap on the device; 200 of them (every
+    third) re-run alone give bit-identical results, flags and digests."""
     torch_cuda()
-    jobs = random_jobs(300, 11)
+    jobs = random_jobs(600, 11)
     srv = S.Server(0, 8 << 30, 64)
     try:
         step("serve mix of %d jobs" % len(jobs))
         ids = [srv.submit(make(j)) for j in jobs]
         got = wait_all(srv, len(jobs))
         peak = srv.stats()
-        for k in range(0, len(jobs), 7):
+        for k in range(0, len(jobs), 3):
             step("serve alone #%d" % k)
             alone = run_alone(srv, jobs[k])
             mixed = got[ids[k]]
