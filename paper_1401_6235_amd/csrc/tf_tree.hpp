@@ -231,16 +231,18 @@ __device__ __forceinline__ Pair<T> tile_value(int64_t tile, int64_t n, bool alig
 
 __device__ __forceinline__ int ilog2(int64_t v) { return 63 - __clzll(v); }
 
-// ---- tile pairs: 8 consecutive leaves per lane --------------------------------
+// ---- tile groups: 8 (binary64) or 16 (binary32) consecutive leaves per lane
 //
-// One wave reduces two adjacent tiles (512 leaves) at once.  Each array is
-// loaded with contiguous 16-byte vectors (lane l, vector k: leaves
-// W (64 k + l) ..), passed through a wave-private LDS region and read back
-// so that lane l holds leaves 8l .. 8l+7: tree levels 1-3 are formed in
-// registers, levels 4-8 by a butterfly over 32 lanes (DPP / swizzle only),
-// leaving the first tile's value in lanes 0-31 and the second's in lanes
-// 32-63.  The LDS region has one spare vector after every lane's group, so
-// the transposed reads are spread over the banks.
+// One wave reduces a group of adjacent tiles at once: 2 tiles (512 leaves)
+// in binary64, 4 tiles (1024 leaves) in binary32, so every pass reads 4 KiB
+// of each array.  Each array is loaded with contiguous 16-byte vectors (lane
+// l, vector k: leaves W (64 k + l) ..), passed through a wave-private LDS
+// region and read back so that lane l holds leaves LPL l .. LPL l + LPL-1;
+// the tree levels inside those leaves are formed in registers and the rest
+// of each tile by a butterfly over its 256 / LPL lanes (DPP / swizzle only),
+// leaving tile q's value in lanes q * 256 / LPL onwards.  The LDS region has
+// one spare vector after every lane's group, spreading the transposed reads
+// over the banks.
 #ifndef TF_RED_PAIRS
 #define TF_RED_PAIRS 1
 #endif
@@ -250,20 +252,28 @@ __device__ __forceinline__ int ilog2(int64_t v) { return 63 - __clzll(v); }
 #ifndef TF_RED_PAIR_ARRAYS
 #define TF_RED_PAIR_ARRAYS 2
 #endif
+#ifndef TF_RED_LPL_F32
+#define TF_RED_LPL_F32 16
+#endif
 
 template <typename T>
 struct PairLayout {
     using V = typename Vec<T>::type;
     static constexpr int W = Vec<T>::N;
-    static constexpr int VPL = 8 / W;      // vectors per lane per array
-    static constexpr int NV = 64 * VPL;    // vectors per array for 512 leaves
+    static constexpr int LPL = sizeof(T) == 8 ? 8 : TF_RED_LPL_F32;  // consecutive leaves per lane
+    static constexpr int VPL = LPL / W;        // vectors per lane per array
+    static constexpr int NV = 64 * VPL;        // vectors per array per pass
+    static constexpr int TILES = 64 * LPL / kTile;  // tiles per pass
+    static constexpr int LANES = kTile / LPL;       // lanes per tile
     static constexpr int SLOTS = TF_RED_LDS_PAD ? NV + NV / VPL : NV;
     __device__ static int slot(int v) { return TF_RED_LDS_PAD ? v + v / VPL : v; }
 };
 
 // One LDS region per kernel, shared by every instantiation (4 waves, sized
-// for binary64, the larger layout).
-constexpr int kPairLdsBytes = 4 * PairLayout<double>::SLOTS * 16;
+// for the larger of the two layouts).
+constexpr int kPairSlots = PairLayout<double>::SLOTS > PairLayout<float>::SLOTS ? PairLayout<double>::SLOTS
+                                                                                : PairLayout<float>::SLOTS;
+constexpr int kPairLdsBytes = 4 * kPairSlots * 16;
 __device__ __forceinline__ void *pair_lds_base() {
     __shared__ __attribute__((aligned(16))) unsigned char buf[kPairLdsBytes];
     return buf;
@@ -280,8 +290,8 @@ __device__ __forceinline__ void pair_load(PairData<T> &D, int64_t tile, int64_t 
     using Tr = LeafTraits<LEAF>;
     using L = PairLayout<T>;
     const int lane = threadIdx.x & 63;
-    const int64_t first = tile * kTile;  // leaf index of the pair's first leaf
-    const bool vec = aligned && first + 2 * kTile <= n;
+    const int64_t first = tile * kTile;  // leaf index of the group's first leaf
+    const bool vec = aligned && first + L::TILES * kTile <= n;
     const T *src[4] = {x0, x1, y0, y1};
     const bool has[4] = {true, Tr::has_x1, Tr::has_y0, Tr::has_y1};
 #pragma unroll
@@ -315,20 +325,20 @@ __device__ __forceinline__ T readlane_t(T v, int l) {
     }
 }
 
-// Values of the two tiles of a loaded pair: lanes 0-31 hold the first tile's,
-// lanes 32-63 the second's.  `lds` is this wave's region of L::SLOTS vectors.
+// Values of the tiles of a loaded group: lanes q * L::LANES .. hold tile q's.
+// `lds` is this wave's region of L::SLOTS vectors.
 template <typename T, int LEAF>
 __device__ __forceinline__ Pair<T> pair_reduce(const PairData<T> &D, typename Vec<T>::type *lds) {
     using Tr = LeafTraits<LEAF>;
     using L = PairLayout<T>;
     const int lane = threadIdx.x & 63;
     const bool has[4] = {true, Tr::has_x1, Tr::has_y0, Tr::has_y1};
-    T lv[4][8];
+    T lv[4][L::LPL];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         if (!has[a]) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) lv[a][i] = T(0);
+            for (int i = 0; i < L::LPL; ++i) lv[a][i] = T(0);
             continue;
         }
 #pragma unroll
@@ -346,17 +356,23 @@ __device__ __forceinline__ Pair<T> pair_reduce(const PairData<T> &D, typename Ve
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    Pair<T> l1[4];
+    // the lane's subtree: level 1 from the leaves, then adjacent pairing
+    Pair<T> t[L::LPL / 2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) l1[i] = level1<T, LEAF>(lv[0], lv[1], lv[2], lv[3], 2 * i);
-    const Pair<T> l2a = node<T, Tr::plain>(l1[0], l1[1]);
-    const Pair<T> l2b = node<T, Tr::plain>(l1[2], l1[3]);
-    Pair<T> v = node<T, Tr::plain>(l2a, l2b);
-    v = butterfly_step<1, T, Tr::plain>(v, lane);
-    v = butterfly_step<2, T, Tr::plain>(v, lane);
-    v = butterfly_step<4, T, Tr::plain>(v, lane);
-    v = butterfly_step<8, T, Tr::plain>(v, lane);
-    return butterfly_step<16, T, Tr::plain>(v, lane);
+    for (int i = 0; i < L::LPL / 2; ++i) t[i] = level1<T, LEAF>(lv[0], lv[1], lv[2], lv[3], 2 * i);
+#pragma unroll
+    for (int w = L::LPL / 2; w > 1; w /= 2) {
+#pragma unroll
+        for (int i = 0; i < w / 2; ++i) t[i] = node<T, Tr::plain>(t[2 * i], t[2 * i + 1]);
+    }
+    Pair<T> v = t[0];
+    if constexpr (L::LANES > 1) v = butterfly_step<1, T, Tr::plain>(v, lane);
+    if constexpr (L::LANES > 2) v = butterfly_step<2, T, Tr::plain>(v, lane);
+    if constexpr (L::LANES > 4) v = butterfly_step<4, T, Tr::plain>(v, lane);
+    if constexpr (L::LANES > 8) v = butterfly_step<8, T, Tr::plain>(v, lane);
+    if constexpr (L::LANES > 16) v = butterfly_step<16, T, Tr::plain>(v, lane);
+    if constexpr (L::LANES > 32) v = butterfly_step<32, T, Tr::plain>(v, lane);
+    return v;
 }
 
 // Butterfly over the first m lanes (m a power of two, at most 64): the
@@ -408,22 +424,25 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
     // three or four input arrays (twofold products) are already near the
     // read bandwidth on single tiles, and the extra transposes cost more
     // than the saved tree levels (measured on MI355X).
-    if (LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS && per_wave >= 2) {  // per_wave: a power of two
+    using PL = PairLayout<T>;
+    if (LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS && per_wave >= PL::TILES) {  // per_wave: a power of two
         typename Vec<T>::type *lds =
-            reinterpret_cast<typename Vec<T>::type *>(pair_lds_base()) + wave * PairLayout<T>::SLOTS;
+            reinterpret_cast<typename Vec<T>::type *>(pair_lds_base()) + wave * PL::SLOTS;
         const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
+        // the next group's loads are in flight while the current one is reduced
         PairData<T> cur, nxt;
         if (t0 < tiles) pair_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
-        for (int p = 0; 2 * p < per_wave; ++p) {
-            const int64_t tile = t0 + 2 * p;
-            if (2 * p + 2 < per_wave && tile + 2 < tiles)
-                pair_load<T, LEAF>(nxt, tile + 2, n, aligned, x0, x1, y0, y1);
+        for (int p = 0; PL::TILES * p < per_wave; ++p) {
+            const int64_t tile = t0 + PL::TILES * p;
+            if (PL::TILES * (p + 1) < per_wave && tile + PL::TILES < tiles)
+                pair_load<T, LEAF>(nxt, tile + PL::TILES, n, aligned, x0, x1, y0, y1);
             if (tile < tiles) {
                 const Pair<T> v = pair_reduce<T, LEAF>(cur, lds);
-                const Pair<T> first{readlane_t(v.hi, 0), readlane_t(v.lo, 0)};
-                const Pair<T> second{readlane_t(v.hi, 32), readlane_t(v.lo, 32)};
-                if (lane == 2 * p) mine = first;
-                if (lane == 2 * p + 1 && tile + 1 < tiles) mine = second;
+#pragma unroll
+                for (int q = 0; q < PL::TILES; ++q) {
+                    const Pair<T> val{readlane_t(v.hi, q * PL::LANES), readlane_t(v.lo, q * PL::LANES)};
+                    if (lane == PL::TILES * p + q && tile + q < tiles) mine = val;
+                }
             }
             cur = nxt;
         }
