@@ -550,6 +550,22 @@ _GROUPS = [
 ]
 
 
+def _bench_dispatches(rows, name_col, grid_col):
+    """Per bench key, the dispatch rows at that kernel's largest grid: the
+    benchmark's own launches (the cache-resident leg launches some of the
+    same kernels over far smaller grids)."""
+    acc = {}
+    for r in rows:
+        k = bench_key(r[name_col])
+        if k:
+            acc.setdefault(k, []).append(r)
+    out = {}
+    for k, rs in acc.items():
+        g = max(int(r[grid_col]) for r in rs)
+        out[k] = (g, [r for r in rs if int(r[grid_col]) == g])
+    return out
+
+
 def summarize_profiles(prof_dir: str, command: str):
     """Write profiles/<group>_kernel_trace.txt, <group>_counters.txt and
     profiles/traffic.json from rocprofv3 runs of this benchmark: kernel
@@ -561,27 +577,30 @@ def summarize_profiles(prof_dir: str, command: str):
     import glob
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
-    stats = glob.glob(os.path.join(prof_dir, "trace", "*kernel_stats.csv"))[0]
-    rows = list(csv.DictReader(open(stats)))
+    trace = glob.glob(os.path.join(prof_dir, "trace", "*kernel_trace.csv"))[0]
+    disp = _bench_dispatches(csv.DictReader(open(trace)), "Kernel_Name", "Grid_Size_X")
+    rows = []  # one per bench key: the launches at the benchmark's own (largest) grid
+    for k, (grid, ds) in disp.items():
+        span = [(float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) for r in ds]
+        rows.append({"key": k, "Name": ds[0]["Kernel_Name"], "Calls": len(ds), "grid": grid,
+                     "AverageNs": sum(span) / len(span), "TotalDurationNs": sum(span)})
     src = kernel_source_hash()
     for fname, what, member in _GROUPS:
         lines = ["# rocprofv3 kernel statistics of " + what,
                  "# command: " + command, "# source hash: " + src,
-                 "%-28s %6s %12s  %s" % ("bench_key", "calls", "avg_us", "kernel")]
-        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-            k = bench_key(r["Name"])
-            if k and member(k):
-                lines.append("%-28s %6s %12.2f  %s" % (k, r["Calls"], float(r["AverageNs"]) / 1e3, r["Name"][:110]))
+                 "# (launches at the benchmark's grid only: the same kernels' smaller launches of the",
+                 "# cache-resident leg, n = 2^20, are left out)",
+                 "%-28s %6s %12s %11s  %s" % ("bench_key", "calls", "avg_us", "grid", "kernel")]
+        for r in sorted(rows, key=lambda r: -r["TotalDurationNs"]):
+            if member(r["key"]):
+                lines.append("%-28s %6d %12.2f %11d  %s" % (r["key"], r["Calls"], r["AverageNs"] / 1e3, r["grid"],
+                                                            r["Name"][:100]))
         open(os.path.join(out_dir, fname + "_kernel_trace.txt"), "w").write("\n".join(lines) + "\n")
 
     def counters(which):
         f = glob.glob(os.path.join(prof_dir, which, "*counter_collection.csv"))[0]
-        acc = {}
-        for r in csv.DictReader(open(f)):
-            k = bench_key(r["Kernel_Name"])
-            if k:
-                acc.setdefault(k, []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+        d = _bench_dispatches(csv.DictReader(open(f)), "Kernel_Name", "Grid_Size")
+        return {k: sum(float(r["Counter_Value"]) for r in ds) / len(ds) for k, (_, ds) in d.items()}
 
     fetch, write = counters("fetch"), counters("write")
     traffic = {"source_hash": src, "command": command, "kernels": {}}
@@ -635,18 +654,13 @@ def summarize_valu(prof_dir: str, command: str, trace_rows):
     over its own dispatch duration)."""
     import csv
     import glob
-    dur = {}
-    for r in trace_rows:
-        k = bench_key(r["Name"])
-        if k:
-            dur[k] = float(r["AverageNs"]) * 1e-9
+    dur = {r["key"]: r["AverageNs"] * 1e-9 for r in trace_rows}
 
     def per_kernel(which):
         f = glob.glob(os.path.join(prof_dir, which, "*counter_collection.csv"))[0]
         acc, span = {}, {}
-        for r in csv.DictReader(open(f)):
-            k = bench_key(r["Kernel_Name"])
-            if k:
+        for k, (_, ds) in _bench_dispatches(csv.DictReader(open(f)), "Kernel_Name", "Grid_Size").items():
+            for r in ds:
                 acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
                 span.setdefault(k, {})[r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
         out = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}

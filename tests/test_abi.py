@@ -62,3 +62,13 @@ def test_host_only_calls():
                              None) == -1
     assert lib.tf_quadratic(tf.TF_F64, i64(3), *([None] * 10), None) == -1
     assert lib.tf_fma(tf.TF_F32, i64(0), *([None] * 8), None) == 0
+
+
+def test_c_consumer_builds():
+    """The C++ consumer of the ABI (run by the GPU tests) compiles and links
+    against the library and the oracle using tf.h alone."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("c_abi_build", os.path.join(ROOT, "tests", "c_abi", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert os.path.exists(mod.build())
