@@ -67,10 +67,14 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the profiled kernels are built from: every HIP
+    source and header of the library except the serving loop's
+    (tf_serve*), which none of the step, chain or application kernels
+    includes."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1401_6235_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name.endswith((".hip", ".hpp")) and not name.startswith("tf_serve"):
             h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -306,15 +310,20 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
         else:
             agree["random"] += 1
             agree["random_flagged"] += r["flag"]
-    def p50(xs):
-        return round(float(np.percentile(np.array(xs), 50)) * 1e6, 1)
+    def pct(xs, q):
+        return round(float(np.percentile(np.array(xs), q)) * 1e6, 1)
 
-    breakdown = {
-        "submit_late_us_p50": p50([r["t_submit"] - r["t_arrive"] for r in res]),
-        "admit_us_p50": p50([r["t_admit"] - r["t_submit"] for r in res]),
-        "materialise_publish_us_p50": p50([r["t_publish"] - r["t_admit"] for r in res]),
-        "device_and_completion_us_p50": p50([r["t_done"] - r["t_publish"] for r in res]),
+    stages = {
+        "submit_late": [r["t_submit"] - r["t_arrive"] for r in res],
+        "admit": [r["t_admit"] - r["t_submit"] for r in res],
+        "materialise_publish": [r["t_publish"] - r["t_admit"] for r in res],
+        "device_and_completion": [r["t_done"] - r["t_publish"] for r in res],
+        # inside device_and_completion, from the device clock: slot opened to
+        # first claim, and first claim to the record
+        "device_queue": [r["queue_us"] * 1e-6 for r in res],
+        "device_run": [r["device_us"] * 1e-6 for r in res],
     }
+    breakdown = {"%s_us_p%d" % (k, q): pct(v, q) for q in (50, 99) for k, v in stages.items()}
     return {
         "jobs": jobs, "completed": len(res), "rate_offered": rate,
         "latency_breakdown": breakdown,

@@ -363,6 +363,7 @@ typedef struct {
     double t_submit;  /* when tfs_submit was called */
     double t_admit, t_publish, t_done; /* admitted, published to the device, completion seen */
     double device_us;              /* first claim to completion on the device */
+    double queue_us;               /* slot opened on the device to its first claim */
 } tfs_result;
 
 typedef struct {

@@ -7,9 +7,11 @@
 // reads the 64 control words (one per lane), picks the job with the fewest
 // unclaimed units (oldest first among equals) and claims a unit with a
 // fetch-add on the control word (wait-free: the returned word says which
-// unit of which job the block owns, or that it came too late); the whole
-// block processes the unit (a 4096-leaf aligned subtree of a sum / dot, or
-// 4096 elements of an axpy / Horner), then bumps the job's done counter.
+// units of which job the block owns, or that it came too late; a large job
+// is claimed several consecutive units at a time); the whole block
+// processes each unit (a 4096-leaf aligned subtree of a sum / dot, or 4096
+// elements of an axpy / Horner), then adds their number to the job's done
+// counter.
 // A block keeps its LDS copy of the descriptor while it keeps claiming
 // units of the same job.  The
 // block that completes a job's last unit joins the per-unit partials and
@@ -119,13 +121,16 @@ __global__ __launch_bounds__(kBlock) void gen_kernel(tfs_desc d) {
 // ---------------------------------------------------------------------------
 
 struct DevSlot {
-    uint64_t ctl;   // TFS_CTL(gen, nclaims, next); 0 = empty
     uint32_t done;  // claims finished
     uint32_t pad;
+    uint64_t t_open;   // dispatcher's clock when it opened the slot
     uint64_t t_start;
     tfs_desc d;
 };
 struct DevState {
+    // The control words sit together (four cache lines), apart from the
+    // descriptors: an idle worker's scan reads them all in one load.
+    uint64_t ctl[TFS_MAX_SLOTS];  // TFS_CTL(gen, nclaims, next); 0 = empty
     DevSlot slot[TFS_MAX_SLOTS];
     uint64_t stop;
 };
@@ -150,22 +155,32 @@ __device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
         const uint64_t pub = ld_acq_sys(&sh->pub_count);
         const bool fresh = consumed < pub;
         while (consumed < pub) {
-            // plain loads after the acquire above: independent, so they
-            // pipeline over the host link instead of one round trip each
-            const tfs_desc *e = &sh->ring[consumed % TFS_RING];
-            const int slot = e->slot;
-            const uint64_t gen = e->gen;
-            const int nclaims = e->nclaims;
+            // The whole entry into registers first, then into the slot: the
+            // loads (plain, after the acquire above) are independent and
+            // share one round trip over the host link.  Copied word by word
+            // from memory to memory, each store could alias the next load
+            // and every word would cost a round trip of its own.
+            constexpr unsigned kWords = sizeof(tfs_desc) / 8;
+            static_assert(sizeof(tfs_desc) % 8 == 0, "descriptor is copied in 8-byte words");
+            const uint64_t *src = (const uint64_t *)&sh->ring[consumed % TFS_RING];
+            uint64_t w[kWords];
+#pragma unroll
+            for (unsigned k = 0; k < kWords; ++k) w[k] = src[k];
+            tfs_desc e;
+            __builtin_memcpy(&e, w, sizeof e);
+            const int slot = e.slot;
+            const uint64_t gen = e.gen;
+            const int nclaims = e.nclaims;
             ++consumed;
             if (slot >= 0 && slot < TFS_MAX_SLOTS) {  // a malformed entry is skipped
                 DevSlot *s = &st->slot[slot];
-                const uint64_t *src = (const uint64_t *)e;
                 uint64_t *dst = (uint64_t *)&s->d;
 #pragma unroll
-                for (unsigned k = 0; k < sizeof(tfs_desc) / 8; ++k) dst[k] = src[k];
+                for (unsigned k = 0; k < kWords; ++k) dst[k] = w[k];
                 s->done = 0;
                 s->t_start = 0;
-                __hip_atomic_store(&s->ctl, TFS_CTL(gen, nclaims, 0), __ATOMIC_RELEASE,
+                s->t_open = wall_clock64();
+                __hip_atomic_store(&st->ctl[slot], TFS_CTL(gen, nclaims, 0), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             st_rel_sys(&sh->consumed, consumed);
@@ -175,7 +190,7 @@ __device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
         if (wall_clock64() - last > idle_ticks) {
             bool busy = false;
             for (int k = 0; k < TFS_MAX_SLOTS; ++k)
-                busy |= __hip_atomic_load(&st->slot[k].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                busy |= __hip_atomic_load(&st->ctl[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             if (!busy) {
                 how = 3;
                 break;
@@ -351,7 +366,7 @@ __device__ void run_claim(const tfs_desc &d, int claim) {
 // ---- completion ------------------------------------------------------------------
 
 template <typename T>
-__device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
+__device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done *rec) {
     tfs_done out = {};
     if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
         const Pair<T> r = block_join<T, false>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
@@ -383,7 +398,8 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
     }
     if (threadIdx.x == 0) {
         // empty the slot first: the host reuses it only after seeing the record
-        __hip_atomic_store(&S->ctl, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctl, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        out.t_open = S->t_open;
         out.t_start = S->t_start;
         out.t_end = wall_clock64();
         out.status = TF_OK;
@@ -397,14 +413,37 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, tfs_done *rec) {
         rec->nonfinite = out.nonfinite;
         rec->hash0 = out.hash0;
         rec->hash1 = out.hash1;
+        rec->t_open = out.t_open;
         rec->t_start = out.t_start;
         rec->t_end = out.t_end;
         st_rel_sys(&rec->gen, d.gen);
     }
 }
 
+// Build-time knobs (results never depend on them): worker blocks per
+// compute unit, and the split of a job's remaining units over the workers
+// that sets the claim batch.
+#ifndef TF_SERVE_WORKERS_PER_CU
+#define TF_SERVE_WORKERS_PER_CU 1
+#endif
+#ifndef TF_SERVE_BATCH_SPLIT
+#define TF_SERVE_BATCH_SPLIT 1
+#endif
+#ifndef TF_SERVE_IDLE_SLEEP
+#define TF_SERVE_IDLE_SLEEP 127  // s_sleep units (64 cycles) between scans of an idle worker
+#endif
+static_assert(TF_SERVE_WORKERS_PER_CU >= 1 && TF_SERVE_WORKERS_PER_CU <= 4, "1 to 4 worker blocks per CU");
+
+// Units per claim when `remaining` units of a job are left and `workers`
+// blocks compete: remaining / (split x workers), between 1 and
+// TFS_MAX_BATCH.
+__device__ __forceinline__ uint64_t batch_for(uint64_t remaining, uint64_t workers) {
+    const uint64_t k = remaining / (TF_SERVE_BATCH_SPLIT * (workers ? workers : 1));
+    return k < 1 ? 1 : k > TFS_MAX_BATCH ? TFS_MAX_BATCH : k;
+}
+
 __device__ void worker(tfs_shared *sh, DevState *st) {
-    __shared__ int s_slot, s_claim, s_last, s_have_slot;
+    __shared__ int s_slot, s_claim, s_count, s_last, s_have_slot;
     __shared__ uint32_t s_gen, s_have_gen;
     __shared__ uint64_t s_desc[sizeof(tfs_desc) / 8];
     const int t = threadIdx.x;
@@ -414,7 +453,7 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
     }
     while (true) {
         if (t < 64) {
-            const uint64_t c = __hip_atomic_load(&st->slot[t].ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t c = __hip_atomic_load(&st->ctl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t gen = TFS_CTL_GEN(c), nt = TFS_CTL_NTILES(c), nx = TFS_CTL_NEXT(c);
             // shortest remaining job first (fewest unclaimed units), then oldest
             const uint64_t key = (gen != 0 && nx < nt) ? ((nt - nx) << 32) | gen : ~0ull;
@@ -435,23 +474,36 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                 // newer job since the scan; an add past the last unit (or on
                 // an empty word, which the next opening overwrites) claims
                 // nothing, and a unit of a newer job is as good as any.
-                const uint64_t old = __hip_atomic_fetch_add(&st->slot[t].ctl, (uint64_t)1, __ATOMIC_ACQ_REL,
+                // Relaxed: the claim publishes nothing, and the one thing it
+                // must see, the descriptor, is acquired below (fence after
+                // this read of the opening's release store) only when the
+                // block's cached copy is for another job.  Each agent-scope
+                // acquire or release costs an L2 invalidate or write-back
+                // on this chip, so the per-unit path keeps a single release.
+                // A large job is claimed a batch of consecutive units at a
+                // time (one fetch-add and one count per batch: atomics on
+                // one word serialise, at tens of nanoseconds each), sized
+                // so that the remaining units still split about twice over
+                // the workers.
+                const uint64_t k = batch_for(nt - nx, gridDim.x - 1);
+                const uint64_t old = __hip_atomic_fetch_add(&st->ctl[t], k, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t g = TFS_CTL_GEN(old);
-                const bool ok = g != 0 && TFS_CTL_NEXT(old) < TFS_CTL_NTILES(old);
+                const uint64_t g = TFS_CTL_GEN(old), first = TFS_CTL_NEXT(old), total = TFS_CTL_NTILES(old);
+                const bool ok = g != 0 && first < total;
                 s_slot = ok ? t : -2;
-                s_claim = (int)TFS_CTL_NEXT(old);
+                s_claim = (int)first;
+                s_count = ok ? (int)(first + k < total ? k : total - first) : 0;
                 s_gen = (uint32_t)g;
             }
         }
         __syncthreads();
-        const int slot = s_slot, claim = s_claim;
+        const int slot = s_slot, claim = s_claim, count = s_count;
         const uint32_t gen = s_gen;
         const bool fresh = slot >= 0 && (slot != s_have_slot || gen != s_have_gen);
         __syncthreads();
         if (slot == -3) break;
         if (slot < 0) {
-            if (slot == -1) __builtin_amdgcn_s_sleep(64);
+            if (slot == -1) __builtin_amdgcn_s_sleep(TF_SERVE_IDLE_SLEEP);
             continue;
         }
         DevSlot *S = &st->slot[slot];
@@ -467,19 +519,25 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
         }
         const tfs_desc &d = *(const tfs_desc *)s_desc;
         if (claim == 0 && t == 0) S->t_start = wall_clock64();
-        if (d.dtype == TF_F64) run_claim<double>(d, claim);
-        else run_claim<float>(d, claim);
+        for (int c = claim; c < claim + count; ++c) {
+            if (d.dtype == TF_F64) run_claim<double>(d, c);
+            else run_claim<float>(d, c);
+        }
         __syncthreads();
         if (t == 0) {
+            // release fence + relaxed count: the block that counts the last
+            // unit reads the end of every other block's release sequence and
+            // acquires them all with the fence below
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint32_t done = __hip_atomic_fetch_add(&S->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            s_last = done + 1 == (uint32_t)d.nclaims;
+            const uint32_t done = __hip_atomic_fetch_add(&S->done, (uint32_t)count, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            s_last = done + (uint32_t)count == (uint32_t)d.nclaims;
         }
         __syncthreads();
         if (s_last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (d.dtype == TF_F64) finalize<double>(d, S, &sh->done[slot]);
-            else finalize<float>(d, S, &sh->done[slot]);
+            if (d.dtype == TF_F64) finalize<double>(d, S, &st->ctl[slot], &sh->done[slot]);
+            else finalize<float>(d, S, &st->ctl[slot], &sh->done[slot]);
         }
         __syncthreads();
     }
@@ -515,7 +573,9 @@ class HipDevice : public tfs::DeviceOps {
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
         tick_hz_ = (double)rate_khz * 1000.0;
-        workers_ = cus;
+        // at most 1024 workers: the claim counter's overshoot bound
+        workers_ = cus * TF_SERVE_WORKERS_PER_CU;
+        if (workers_ > 1024) workers_ = 1024;
         events_.resize(2 * TFS_MAX_SLOTS);
         for (auto &e : events_) {
             if (hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess) return TF_EDEVICE;

@@ -10,6 +10,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -187,6 +188,10 @@ class Server {
 
     void shutdown() {
         if (running_.exchange(false)) {
+            {
+                std::lock_guard<std::mutex> g(in_mu_);  // a parked server thread sees running_ false
+            }
+            in_cv_.notify_one();
             if (thread_.joinable()) thread_.join();
             dev_->stop();
         }
@@ -204,10 +209,13 @@ class Server {
         q.plan = p;
         q.t_submit = now_s();
         q.t_arrive = t_arrive > 0 ? t_arrive : q.t_submit;
-        std::lock_guard<std::mutex> g(in_mu_);
-        q.id = ++next_id_;
-        inbox_.push_back(q);
-        if (id) *id = q.id;
+        {
+            std::lock_guard<std::mutex> g(in_mu_);
+            q.id = ++next_id_;
+            inbox_.push_back(q);
+            if (id) *id = q.id;
+        }
+        in_cv_.notify_one();  // wakes the server thread if it is parked
         return TF_OK;
     }
 
@@ -400,6 +408,7 @@ class Server {
         r.t_publish = s.t_publish;
         r.t_done = now_s();
         r.device_us = d.t_end > d.t_start ? (double)(d.t_end - d.t_start) * 1e6 / tick_hz_ : 0.0;
+        r.queue_us = d.t_start > d.t_open && d.t_open ? (double)(d.t_start - d.t_open) * 1e6 / tick_hz_ : 0.0;
         {
             std::lock_guard<std::mutex> g(out_mu_);
             completed_.push_back(r);
@@ -407,9 +416,14 @@ class Server {
         ++n_completed_;
     }
 
-    // Server thread: owns pending_, slots_ and pool_ without locks.
+    // Server thread: owns pending_, slots_ and pool_ without locks.  It polls
+    // without sleeping while jobs are queued or in flight and for a grace
+    // period after the last progress (a timed sleep costs tens of
+    // microseconds per stage, more than a small job's device time), then
+    // parks on in_cv_ until a submit, waking once a millisecond for the
+    // liveness check.
     void loop() {
-        double next_check = 0.0;
+        double next_check = 0.0, last_progress = now_s();
         while (running_) {
             {
                 std::lock_guard<std::mutex> g(in_mu_);
@@ -429,9 +443,20 @@ class Server {
                 alive_ = alive;
                 if (!alive && running_) dev_->start();  // drained after an idle period: relaunch
             }
-            if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(5));
+            if (progress) {
+                last_progress = t;
+            } else if (in_flight_.load() > 0 || !pending_.empty() || t - last_progress < kSpinGrace) {
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> g(in_mu_);
+                // system_clock: a timed wait on it is pthread_cond_timedwait,
+                // which thread sanitizers know (the steady_clock form is not)
+                in_cv_.wait_until(g, std::chrono::system_clock::now() + std::chrono::milliseconds(1),
+                                  [this] { return !inbox_.empty() || !running_; });
+            }
         }
     }
+    static constexpr double kSpinGrace = 2e-3;  // seconds of polling after the last progress
 
     DeviceOps *dev_;
     Pool pool_;
@@ -441,6 +466,7 @@ class Server {
     std::deque<Pending> pending_;    // queued for admission (server thread only)
     std::deque<tfs_result> completed_;  // out_mu_
     std::mutex in_mu_, out_mu_;
+    std::condition_variable in_cv_;  // inbox non-empty or shutdown (with in_mu_)
     std::thread thread_;
     std::atomic<bool> running_{false}, alive_{true};
     uint64_t next_id_ = 0, gen_ = 0, published_ = 0;

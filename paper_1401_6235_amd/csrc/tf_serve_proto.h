@@ -28,13 +28,15 @@
 #define TFS_CLAIM 4096         /* elements per claimed unit of work */
 #define TFS_MAX_CLAIMS 16383   /* claims per job (14-bit field) */
 #define TFS_MAX_N ((int64_t)TFS_CLAIM * TFS_MAX_CLAIMS)
+#define TFS_MAX_BATCH 16       /* units claimed by one fetch-add, at most */
 
 /* Control word of a device slot: generation (low 32 bits of the
  * publication number, never 0), number of claims (14 bits), next unclaimed
  * claim (18 bits).  gen == 0: slot empty.  Workers claim with a fetch-add of
- * 1; a worker adds only after it has seen next < claims, so the count runs
- * past the number of claims by at most the number of workers and never
- * reaches the claims field. */
+ * 1 .. TFS_MAX_BATCH units; a worker adds only after it has seen
+ * next < claims, so the count runs past the number of claims by at most
+ * TFS_MAX_BATCH times the number of workers (at most 1024:
+ * 16383 + 16 x 1024 < 2^18) and never reaches the claims field. */
 #define TFS_CTL(gen, ntiles, next)                                                   \
     (((uint64_t)(uint32_t)(gen) << 32) | ((uint64_t)(ntiles) << 18) | (uint64_t)(next))
 #define TFS_CTL_GEN(c) ((c) >> 32)
@@ -70,6 +72,7 @@ typedef struct {
     uint64_t n_flagged;    /* vector jobs: elements with |z1_i| > thr |z0_i| */
     uint64_t nonfinite;    /* elements (or results) that are not finite */
     uint64_t hash0, hash1; /* vector jobs: sum of the bit patterns, mod 2^64 */
+    uint64_t t_open;         /* device wall clock: slot opened by the dispatcher */
     uint64_t t_start, t_end; /* device wall clock of first claim / finish */
 } tfs_done;
 
