@@ -316,11 +316,12 @@ def serving_run(torch, W, jobs=20000, rate=2000.0, budget=64 << 30, seed=1):
     stages = {
         "submit_late": [r["t_submit"] - r["t_arrive"] for r in res],
         "admit": [r["t_admit"] - r["t_submit"] for r in res],
-        "materialise_publish": [r["t_publish"] - r["t_admit"] for r in res],
+        "publish": [r["t_publish"] - r["t_admit"] for r in res],
         "device_and_completion": [r["t_done"] - r["t_publish"] for r in res],
         # inside device_and_completion, from the device clock: slot opened to
-        # first claim, and first claim to the record
+        # first unit claimed, input generation, compute units to the record
         "device_queue": [r["queue_us"] * 1e-6 for r in res],
+        "device_gen": [r["gen_us"] * 1e-6 for r in res],
         "device_run": [r["device_us"] * 1e-6 for r in res],
     }
     breakdown = {"%s_us_p%d" % (k, q): pct(v, q) for q in (50, 99) for k, v in stages.items()}

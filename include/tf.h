@@ -306,10 +306,11 @@ int64_t tf_config(int key, int64_t value);
  * admitted while a slot (at most TFS_MAX_SLOTS in flight) and room in the
  * server's HBM pool (budget_bytes: the job's generated inputs, outputs and
  * partials) are free; the head of the queue waits otherwise.  An admitted
- * job's inputs are materialised on the device, its descriptor is published
- * to the device job table, and the persistent kernel's workers claim its
- * 16384-element units alongside those of every other job in flight, oldest
- * job first.  Reductions use the same fixed tree as tf_sum / tf_dot and
+ * job's descriptor is published to the device job table, and the
+ * persistent kernel's workers claim its 4096-element units alongside those
+ * of every other job in flight, the job with the least work left first: a
+ * job with generated inputs first runs units that write them, then its
+ * compute units.  Reductions use the same fixed tree as tf_sum / tf_dot and
  * elementwise results are per element, so a job's result is bit for bit the
  * same alone or in any mix.
  *
@@ -362,8 +363,9 @@ typedef struct {
     double t_arrive;  /* scheduled arrival (tfs_submit argument), tfs_clock() seconds */
     double t_submit;  /* when tfs_submit was called */
     double t_admit, t_publish, t_done; /* admitted, published to the device, completion seen */
-    double device_us;              /* first claim to completion on the device */
-    double queue_us;               /* slot opened on the device to its first claim */
+    double queue_us;               /* slot opened on the device to its first unit claimed */
+    double gen_us;                 /* generation of RANDOM / ILLCOND inputs on the device */
+    double device_us;              /* compute units: inputs ready to the record written */
 } tfs_result;
 
 typedef struct {

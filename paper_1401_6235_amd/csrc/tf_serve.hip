@@ -21,8 +21,10 @@
 // the stop flag and no unit is left, and the dispatcher itself exits on the
 // host's stop request or after a long idle period.
 //
-// Inputs of RANDOM / ILLCOND jobs are materialised by a separate generator
-// kernel on a side stream before the job is published.
+// Inputs of RANDOM / ILLCOND jobs are written by the workers themselves, in
+// a generation phase of the job that precedes its compute units (the
+// persistent kernel never waits for another kernel: streams share a few
+// hardware queues, and a second kernel may be queued behind this one).
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -89,30 +91,48 @@ __device__ __forceinline__ double cancel_scale<double>() { return 0x1p-40; }
 template <>
 __device__ __forceinline__ float cancel_scale<float>() { return 0x1p-16f; }
 
+// Element i of every input array the job generates.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void gen_kernel(tfs_desc d) {
+__device__ __forceinline__ void gen_elem(T *x0, T *x1, T *y0, T *y1, uint64_t s, int64_t i, bool horner, bool ill,
+                                         T a0) {
+    T a;
+    if (horner) {
+        if (ill) a = T(1) + gen_u<T>(draw(s, i, 0)) * T(0x1p-12);
+        else a = T(0.9) + T(0.2) * gen_u01<T>(draw(s, i, 0));
+    } else {
+        a = gen_value<T>(draw(s, i, 0));
+    }
+    x0[i] = a;
+    if (x1) x1[i] = a * (gen_u<T>(draw(s, i, 1)) * low_scale<T>());
+    if (y0) {
+        T b;
+        if (!horner && ill)  // axpy with y ~ -a x
+            b = -(a0 * a) + a * (gen_u<T>(draw(s, i, 2)) * cancel_scale<T>());
+        else
+            b = gen_value<T>(draw(s, i, 2));
+        y0[i] = b;
+        if (y1) y1[i] = b * (gen_u<T>(draw(s, i, 3)) * low_scale<T>());
+    }
+}
+
+// One generation unit: elements [unit * TFS_CLAIM, (unit + 1) * TFS_CLAIM) of
+// every input array the job generates, consecutive threads on consecutive
+// elements; a full unit in a loop of fixed length, unrolled so that the
+// independent elements' arithmetic and stores overlap.
+template <typename T>
+__device__ void gen_unit(const tfs_desc &d, int unit) {
     T *x0 = (T *)d.x0, *x1 = (T *)d.x1, *y0 = (T *)d.y0, *y1 = (T *)d.y1;
     const uint64_t s = d.seed;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < d.n; i += step) {
-        T a;
-        if (d.op == TFS_OP_HORNER) {
-            if (d.kind == TFS_KIND_ILLCOND) a = T(1) + gen_u<T>(draw(s, i, 0)) * T(0x1p-12);
-            else a = T(0.9) + T(0.2) * gen_u01<T>(draw(s, i, 0));
-        } else {
-            a = gen_value<T>(draw(s, i, 0));
-        }
-        x0[i] = a;
-        if (x1) x1[i] = a * (gen_u<T>(draw(s, i, 1)) * low_scale<T>());
-        if (y0) {
-            T b;
-            if (d.op == TFS_OP_AXPY && d.kind == TFS_KIND_ILLCOND)
-                b = -(T(d.a0) * a) + a * (gen_u<T>(draw(s, i, 2)) * cancel_scale<T>());
-            else
-                b = gen_value<T>(draw(s, i, 2));
-            y0[i] = b;
-            if (y1) y1[i] = b * (gen_u<T>(draw(s, i, 3)) * low_scale<T>());
-        }
+    const bool horner = d.op == TFS_OP_HORNER, ill = d.kind == TFS_KIND_ILLCOND;
+    const T a0 = T(d.a0);
+    const int64_t base = (int64_t)unit * TFS_CLAIM;
+    const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
+    if (end - base == TFS_CLAIM) {
+#pragma unroll 4
+        for (int k = 0; k < TFS_CLAIM / kBlock; ++k)
+            gen_elem<T>(x0, x1, y0, y1, s, base + k * kBlock + threadIdx.x, horner, ill, a0);
+    } else {
+        for (int64_t i = base + threadIdx.x; i < end; i += kBlock) gen_elem<T>(x0, x1, y0, y1, s, i, horner, ill, a0);
     }
 }
 
@@ -121,16 +141,17 @@ __global__ __launch_bounds__(kBlock) void gen_kernel(tfs_desc d) {
 // ---------------------------------------------------------------------------
 
 struct DevSlot {
-    uint32_t done;  // claims finished
+    uint32_t done;  // units of the current phase finished
     uint32_t pad;
     uint64_t t_open;   // dispatcher's clock when it opened the slot
-    uint64_t t_start;
+    uint64_t t_start;  // first unit claimed
+    uint64_t t_ready;  // compute phase opened after generation (0: provided inputs)
     tfs_desc d;
 };
 struct DevState {
     // The control words sit together (four cache lines), apart from the
     // descriptors: an idle worker's scan reads them all in one load.
-    uint64_t ctl[TFS_MAX_SLOTS];  // TFS_CTL(gen, nclaims, next); 0 = empty
+    uint64_t ctl[TFS_MAX_SLOTS];  // TFS_CTL(gen, phase, units, next); 0 = empty
     DevSlot slot[TFS_MAX_SLOTS];
     uint64_t stop;
 };
@@ -179,9 +200,11 @@ __device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
                 for (unsigned k = 0; k < kWords; ++k) dst[k] = w[k];
                 s->done = 0;
                 s->t_start = 0;
+                s->t_ready = 0;
                 s->t_open = wall_clock64();
-                __hip_atomic_store(&st->ctl[slot], TFS_CTL(gen, nclaims, 0), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t open = e.ngen > 0 ? TFS_CTL(gen, TFS_PHASE_GEN, e.ngen, 0)
+                                                 : TFS_CTL(gen, TFS_PHASE_COMPUTE, nclaims, 0);
+                __hip_atomic_store(&st->ctl[slot], open, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
             st_rel_sys(&sh->consumed, consumed);
         }
@@ -401,6 +424,7 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
         __hip_atomic_store(ctl, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         out.t_open = S->t_open;
         out.t_start = S->t_start;
+        out.t_ready = S->t_ready;
         out.t_end = wall_clock64();
         out.status = TF_OK;
         rec->status = out.status;
@@ -415,6 +439,7 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
         rec->hash1 = out.hash1;
         rec->t_open = out.t_open;
         rec->t_start = out.t_start;
+        rec->t_ready = out.t_ready;
         rec->t_end = out.t_end;
         st_rel_sys(&rec->gen, d.gen);
     }
@@ -443,13 +468,14 @@ __device__ __forceinline__ uint64_t batch_for(uint64_t remaining, uint64_t worke
 }
 
 __device__ void worker(tfs_shared *sh, DevState *st) {
-    __shared__ int s_slot, s_claim, s_count, s_last, s_have_slot;
+    __shared__ int s_slot, s_claim, s_count, s_phase, s_last, s_have_slot, s_have_phase;
     __shared__ uint32_t s_gen, s_have_gen;
     __shared__ uint64_t s_desc[sizeof(tfs_desc) / 8];
     const int t = threadIdx.x;
     if (t == 0) {
         s_have_slot = -1;
         s_have_gen = 0;
+        s_have_phase = -1;
     }
     while (true) {
         if (t < 64) {
@@ -493,13 +519,16 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                 s_slot = ok ? t : -2;
                 s_claim = (int)first;
                 s_count = ok ? (int)(first + k < total ? k : total - first) : 0;
+                s_phase = (int)TFS_CTL_PHASE(old);
                 s_gen = (uint32_t)g;
             }
         }
         __syncthreads();
-        const int slot = s_slot, claim = s_claim, count = s_count;
+        const int slot = s_slot, claim = s_claim, count = s_count, phase = s_phase;
         const uint32_t gen = s_gen;
-        const bool fresh = slot >= 0 && (slot != s_have_slot || gen != s_have_gen);
+        // A new job, or the compute phase of a job whose inputs other blocks
+        // have just generated: acquire (descriptor, inputs) before use.
+        const bool fresh = slot >= 0 && (slot != s_have_slot || gen != s_have_gen || phase != s_have_phase);
         __syncthreads();
         if (slot == -3) break;
         if (slot < 0) {
@@ -514,14 +543,21 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
             if (t == 0) {
                 s_have_slot = slot;
                 s_have_gen = gen;
+                s_have_phase = phase;
             }
             __syncthreads();
         }
         const tfs_desc &d = *(const tfs_desc *)s_desc;
-        if (claim == 0 && t == 0) S->t_start = wall_clock64();
+        const bool gen_phase = phase == TFS_PHASE_GEN;
+        if (claim == 0 && t == 0 && (gen_phase || d.ngen == 0)) S->t_start = wall_clock64();
         for (int c = claim; c < claim + count; ++c) {
-            if (d.dtype == TF_F64) run_claim<double>(d, c);
-            else run_claim<float>(d, c);
+            if (gen_phase) {
+                if (d.dtype == TF_F64) gen_unit<double>(d, c);
+                else gen_unit<float>(d, c);
+            } else {
+                if (d.dtype == TF_F64) run_claim<double>(d, c);
+                else run_claim<float>(d, c);
+            }
         }
         __syncthreads();
         if (t == 0) {
@@ -531,13 +567,27 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint32_t done = __hip_atomic_fetch_add(&S->done, (uint32_t)count, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
-            s_last = done + (uint32_t)count == (uint32_t)d.nclaims;
+            s_last = done + (uint32_t)count == (uint32_t)(gen_phase ? d.ngen : d.nclaims);
         }
         __syncthreads();
         if (s_last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (d.dtype == TF_F64) finalize<double>(d, S, &st->ctl[slot], &sh->done[slot]);
-            else finalize<float>(d, S, &st->ctl[slot], &sh->done[slot]);
+            if (gen_phase) {
+                // Every input is written: reopen the slot for the compute
+                // units (a late add of the generation phase that lands after
+                // this store is a valid claim of a compute unit; one before
+                // it claimed nothing and is overwritten).
+                if (t == 0) {
+                    S->done = 0;
+                    S->t_ready = wall_clock64();
+                    __hip_atomic_store(&st->ctl[slot], TFS_CTL(d.gen, TFS_PHASE_COMPUTE, d.nclaims, 0),
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else if (d.dtype == TF_F64) {
+                finalize<double>(d, S, &st->ctl[slot], &sh->done[slot]);
+            } else {
+                finalize<float>(d, S, &st->ctl[slot], &sh->done[slot]);
+            }
         }
         __syncthreads();
     }
@@ -568,7 +618,6 @@ class HipDevice : public tfs::DeviceOps {
         if (hipMalloc(&state_, sizeof(DevState)) != hipSuccess) return TF_ENOMEM;
         if (hipMemset(state_, 0, sizeof(DevState)) != hipSuccess) return TF_EDEVICE;
         if (hipStreamCreateWithFlags(&work_, hipStreamNonBlocking) != hipSuccess) return TF_EDEVICE;
-        if (hipStreamCreateWithFlags(&gen_, hipStreamNonBlocking) != hipSuccess) return TF_EDEVICE;
         int rate_khz = 100000, cus = 256;
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -576,21 +625,12 @@ class HipDevice : public tfs::DeviceOps {
         // at most 1024 workers: the claim counter's overshoot bound
         workers_ = cus * TF_SERVE_WORKERS_PER_CU;
         if (workers_ > 1024) workers_ = 1024;
-        events_.resize(2 * TFS_MAX_SLOTS);
-        for (auto &e : events_) {
-            if (hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess) return TF_EDEVICE;
-            e.used = false;
-        }
         return TF_OK;
     }
     ~HipDevice() override {
         if (device_ >= 0) (void)hipSetDevice(device_);
         if (work_) (void)hipStreamSynchronize(work_);
-        if (gen_) (void)hipStreamSynchronize(gen_);
-        for (auto &e : events_)
-            if (e.ev) (void)hipEventDestroy(e.ev);
         if (work_) (void)hipStreamDestroy(work_);
-        if (gen_) (void)hipStreamDestroy(gen_);
         if (state_) (void)hipFree(state_);
         if (shared_) (void)hipHostFree(shared_);
         if (pool_) (void)hipFree(pool_);
@@ -603,7 +643,11 @@ class HipDevice : public tfs::DeviceOps {
         __atomic_store_n(&shared_->stop, 0, __ATOMIC_RELEASE);
         const uint64_t zero = 0;
         if (hipMemcpy(&state_->stop, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return TF_EDEVICE;
-        const uint64_t idle = (uint64_t)(30.0 * tick_hz_);  // drain after 30 s without work
+        __atomic_store_n(&shared_->kernel_state, 1, __ATOMIC_RELEASE);  // launched: no second launch on publish
+        // Drain after 20 ms without work: the kernel's hardware queue may be
+        // shared with other streams of the process, whose work waits until
+        // it exits; the host relaunches it with the next job.
+        const uint64_t idle = (uint64_t)(0.02 * tick_hz_);
         hipLaunchKernelGGL(serve_kernel, dim3(1 + workers_), dim3(kBlock), 0, work_, shared_, state_, idle);
         return hipGetLastError() == hipSuccess ? TF_OK : TF_EDEVICE;
     }
@@ -612,37 +656,13 @@ class HipDevice : public tfs::DeviceOps {
         __atomic_store_n(&shared_->stop, 1, __ATOMIC_RELEASE);
         return hipStreamSynchronize(work_) == hipSuccess ? TF_OK : TF_EDEVICE;
     }
-    int materialize(const tfs_desc &d, int *token) override {
-        int k = -1;
-        for (size_t i = 0; i < events_.size(); ++i)
-            if (!events_[i].used) {
-                k = (int)i;
-                break;
-            }
-        if (k < 0) return TF_EBUSY;
-        events_[k].used = true;
-        int64_t blocks = (d.n + kBlock - 1) / kBlock;
-        if (blocks > 8 * workers_) blocks = 8 * workers_;
-        if (d.dtype == TF_F64) hipLaunchKernelGGL(gen_kernel<double>, dim3((unsigned)blocks), dim3(kBlock), 0, gen_, d);
-        else hipLaunchKernelGGL(gen_kernel<float>, dim3((unsigned)blocks), dim3(kBlock), 0, gen_, d);
-        (void)hipEventRecord(events_[k].ev, gen_);
-        *token = k;
-        return TF_OK;
-    }
-    bool materialized(int token) override { return hipEventQuery(events_[token].ev) == hipSuccess; }
-    void release_token(int token) override { events_[token].used = false; }
 
   private:
-    struct Ev {
-        hipEvent_t ev = nullptr;
-        bool used = false;
-    };
     int device_ = -1;
     void *pool_ = nullptr;
     tfs_shared *shared_ = nullptr;
     DevState *state_ = nullptr;
-    hipStream_t work_ = nullptr, gen_ = nullptr;
-    std::vector<Ev> events_;
+    hipStream_t work_ = nullptr;
     double tick_hz_ = 1e8;
     int workers_ = 256;
 };

@@ -1,6 +1,9 @@
 // Host side of the serving loop: job validation and sizing, the pool
 // sub-allocator, admission (FIFO, by HBM bytes and free slots), publication
-// into the descriptor ring and completion handling.  Pure C++: the device is
+// into the descriptor ring and completion handling.  Inputs that a job
+// generates from its seed are written by the persistent kernel itself, in
+// the job's first phase: nothing else runs on the device beside it, so its
+// progress never waits for a second kernel to be scheduled.  Pure C++: the device is
 // reached only through the DeviceOps interface, implemented over HIP by the
 // library and by a CPU stand-in in the host-logic tests.
 #pragma once
@@ -84,6 +87,7 @@ struct Plan {
     uint64_t off_x0 = 0, off_x1 = 0, off_y0 = 0, off_y1 = 0, off_z0 = 0, off_z1 = 0, off_part = 0;
     bool gen_x1 = false, gen_y0 = false, gen_y1 = false;
     int nclaims = 0, tiles_per_claim = 0, padded = 0;
+    int ngen = 0;  // units of TFS_CLAIM elements generating the inputs
 };
 
 inline int64_t pow2_ceil(int64_t v) {
@@ -126,6 +130,7 @@ inline int plan_job(const tfs_job &j, Plan *p) {
         if (p->gen_x1) take(&p->off_x1, arr);
         if (p->gen_y0) take(&p->off_y0, arr);
         if (p->gen_y1) take(&p->off_y1, arr);
+        p->ngen = (int)((j.n + TFS_CLAIM - 1) / TFS_CLAIM);
     }
     if (reduce) {
         const int64_t tiles = (j.n + 255) / 256;
@@ -157,9 +162,6 @@ class DeviceOps {
     virtual int start() = 0;                   // start the persistent worker
     virtual bool running() = 0;                // worker still alive
     virtual int stop() = 0;                    // ask the worker to drain and wait for it
-    virtual int materialize(const tfs_desc &d, int *token) = 0;  // generate inputs
-    virtual bool materialized(int token) = 0;  // generation of `token` finished
-    virtual void release_token(int token) = 0;
 };
 
 inline double now_s() {
@@ -254,8 +256,6 @@ class Server {
     };
     struct Slot {
         bool busy;
-        int stage;  // 1 generating, 2 published
-        int token;
         Pending job;
         tfs_desc desc;
         uint64_t off;
@@ -279,6 +279,7 @@ class Server {
         d.nclaims = p.nclaims;
         d.tiles_per_claim = p.tiles_per_claim;
         d.padded = p.padded;
+        d.ngen = p.ngen;
         const bool f32 = j.dtype == TF_F32;
         d.a0 = f32 ? (double)(float)j.a[0] : j.a[0];
         d.a1 = f32 ? (double)(float)j.a[1] : j.a[1];
@@ -332,14 +333,7 @@ class Server {
             resident_ = resident;
             if (resident > peak_resident_) peak_resident_ = resident;
             ++in_flight_;
-            if (s.job.job.kind == TFS_KIND_PROVIDED) {
-                s.token = -1;
-                s.stage = 2;
-                publish(s);
-            } else {
-                s.stage = 1;
-                dev_->materialize(s.desc, &s.token);
-            }
+            publish(s);
             progress = true;
         }
         return progress;
@@ -347,6 +341,9 @@ class Server {
 
     void publish(Slot &s) {
         tfs_shared *sh = dev_->shared();
+        // drained after an idle period (the kernel says so in shared memory;
+        // the stream query confirms it): relaunch before publishing
+        if (__atomic_load_n(&sh->kernel_state, __ATOMIC_ACQUIRE) >= 2 && !dev_->running()) dev_->start();
         const uint64_t seq = published_;
         while (seq - __atomic_load_n(&sh->consumed, __ATOMIC_ACQUIRE) >= TFS_RING)
             std::this_thread::yield();  // ring full: wait for the dispatcher
@@ -363,22 +360,14 @@ class Server {
         for (int i = 0; i < max_slots_; ++i) {
             Slot &s = slots_[i];
             if (!s.busy) continue;
-            if (s.stage == 1 && dev_->materialized(s.token)) {
-                dev_->release_token(s.token);
-                s.stage = 2;
-                publish(s);
+            const uint64_t g = __atomic_load_n(&sh->done[i].gen, __ATOMIC_ACQUIRE);
+            if (g == s.desc.gen) {
+                pool_.release(s.off, s.job.plan.bytes);
+                resident_ = pool_.capacity() - pool_.free_bytes();
+                s.busy = false;
+                --in_flight_;
+                complete(s, sh->done[i]);
                 progress = true;
-            }
-            if (s.stage == 2) {
-                const uint64_t g = __atomic_load_n(&sh->done[i].gen, __ATOMIC_ACQUIRE);
-                if (g == s.desc.gen) {
-                    pool_.release(s.off, s.job.plan.bytes);
-                    resident_ = pool_.capacity() - pool_.free_bytes();
-                    s.busy = false;
-                    --in_flight_;
-                    complete(s, sh->done[i]);
-                    progress = true;
-                }
             }
         }
         return progress;
@@ -407,8 +396,11 @@ class Server {
         r.t_admit = s.t_admit;
         r.t_publish = s.t_publish;
         r.t_done = now_s();
-        r.device_us = d.t_end > d.t_start ? (double)(d.t_end - d.t_start) * 1e6 / tick_hz_ : 0.0;
-        r.queue_us = d.t_start > d.t_open && d.t_open ? (double)(d.t_start - d.t_open) * 1e6 / tick_hz_ : 0.0;
+        auto us = [this](uint64_t a, uint64_t b) { return a && b > a ? (double)(b - a) * 1e6 / tick_hz_ : 0.0; };
+        const uint64_t compute_from = d.t_ready ? d.t_ready : d.t_start;
+        r.queue_us = us(d.t_open, d.t_start);
+        r.gen_us = d.t_ready ? us(d.t_start, d.t_ready) : 0.0;
+        r.device_us = us(compute_from, d.t_end);
         {
             std::lock_guard<std::mutex> g(out_mu_);
             completed_.push_back(r);

@@ -11,7 +11,10 @@
  * stores pub_count = seq + 1 with release semantics.  The kernel's
  * dispatcher wave reads pub_count with acquire (system scope), copies each
  * new descriptor into the device slot table and opens the slot by a
- * release store of its control word.
+ * release store of its control word.  A job whose inputs are generated on
+ * the device opens in the generation phase: its units first write the
+ * inputs, and the block that finishes the last of them reopens the slot in
+ * the compute phase.
  *
  * Completion: the worker that finishes a job's last claim writes the
  * job's done record, its `gen` field last with a system-scope release;
@@ -31,17 +34,22 @@
 #define TFS_MAX_BATCH 16       /* units claimed by one fetch-add, at most */
 
 /* Control word of a device slot: generation (low 32 bits of the
- * publication number, never 0), number of claims (14 bits), next unclaimed
- * claim (18 bits).  gen == 0: slot empty.  Workers claim with a fetch-add of
- * 1 .. TFS_MAX_BATCH units; a worker adds only after it has seen
- * next < claims, so the count runs past the number of claims by at most
+ * publication number, never 0), phase (1 bit: TFS_PHASE_GEN or
+ * TFS_PHASE_COMPUTE), number of units in the phase (14 bits), next
+ * unclaimed unit (17 bits).  gen == 0: slot empty.  Workers claim with a
+ * fetch-add of 1 .. TFS_MAX_BATCH units; a worker adds only after it has
+ * seen next < units, so the count runs past the number of units by at most
  * TFS_MAX_BATCH times the number of workers (at most 1024:
- * 16383 + 16 x 1024 < 2^18) and never reaches the claims field. */
-#define TFS_CTL(gen, ntiles, next)                                                   \
-    (((uint64_t)(uint32_t)(gen) << 32) | ((uint64_t)(ntiles) << 18) | (uint64_t)(next))
+ * 16383 + 16 x 1024 < 2^17) and never reaches the units field. */
+#define TFS_PHASE_COMPUTE 0
+#define TFS_PHASE_GEN 1
+#define TFS_CTL(gen, phase, ntiles, next)                                                          \
+    (((uint64_t)(uint32_t)(gen) << 32) | ((uint64_t)(phase) << 31) | ((uint64_t)(ntiles) << 17) | \
+     (uint64_t)(next))
 #define TFS_CTL_GEN(c) ((c) >> 32)
-#define TFS_CTL_NTILES(c) (((c) >> 18) & 0x3fffu)
-#define TFS_CTL_NEXT(c) ((c)&0x3ffffu)
+#define TFS_CTL_PHASE(c) (((c) >> 31) & 1u)
+#define TFS_CTL_NTILES(c) (((c) >> 17) & 0x3fffu)
+#define TFS_CTL_NEXT(c) ((c)&0x1ffffu)
 
 typedef struct {
     uint64_t gen;      /* publication number, 1, 2, ... */
@@ -55,6 +63,8 @@ typedef struct {
     int32_t nclaims;   /* claims of TFS_CLAIM elements */
     int32_t tiles_per_claim; /* reductions: 256-leaf tiles per claim (power of two) */
     int32_t padded;    /* reductions: claims padded to a power of two */
+    int32_t ngen;      /* units of TFS_CLAIM elements that generate the inputs (0: provided) */
+    int32_t pad0;
     double a0, a1;     /* axpy scalar, already rounded to dtype */
     double thr;        /* flag threshold on |z1| / |z0| */
     double c[33];      /* Horner coefficients, already rounded to dtype */
@@ -72,8 +82,10 @@ typedef struct {
     uint64_t n_flagged;    /* vector jobs: elements with |z1_i| > thr |z0_i| */
     uint64_t nonfinite;    /* elements (or results) that are not finite */
     uint64_t hash0, hash1; /* vector jobs: sum of the bit patterns, mod 2^64 */
-    uint64_t t_open;         /* device wall clock: slot opened by the dispatcher */
-    uint64_t t_start, t_end; /* device wall clock of first claim / finish */
+    uint64_t t_open;  /* device wall clock: slot opened by the dispatcher */
+    uint64_t t_start; /* first unit claimed */
+    uint64_t t_ready; /* inputs generated, compute phase opened (0: provided inputs) */
+    uint64_t t_end;   /* record written */
 } tfs_done;
 
 /* Host-coherent shared region. */

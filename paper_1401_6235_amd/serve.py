@@ -1,7 +1,7 @@
 """Python binding of the serving API (tfs_* in include/tf.h).
 
 Argument marshalling only: jobs are plain descriptors handed to the native
-server, which admits them, materialises their inputs on the GPU and runs
+server, which admits them, generates their inputs on the GPU and runs
 them in the library's persistent kernel.
 """
 from __future__ import annotations
@@ -30,8 +30,8 @@ class TfsResult(C.Structure):
                 ("z1", C.c_double), ("max_abs_z0", C.c_double), ("max_abs_z1", C.c_double),
                 ("n_flagged", C.c_uint64), ("nonfinite", C.c_uint64), ("hash_z0", C.c_uint64),
                 ("hash_z1", C.c_uint64), ("t_arrive", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_publish", C.c_double), ("t_done", C.c_double), ("device_us", C.c_double),
-                ("queue_us", C.c_double)]
+                ("t_publish", C.c_double), ("t_done", C.c_double), ("queue_us", C.c_double),
+                ("gen_us", C.c_double), ("device_us", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -3,8 +3,8 @@
 // The stand-in implements the same DeviceOps interface as the HIP backend:
 // a thread plays the persistent kernel's dispatcher and workers (it reads
 // the descriptor ring with acquire loads, "processes" each job after a short
-// delay and writes the completion record, generation last with release),
-// and materialisation completes after a delay.  Results are not arithmetic
+// delay and writes the completion record, generation last with release).
+// Results are not arithmetic
 // (z0 = n, z1 = gen): the scenarios check admission, slot recycling,
 // budget waits, ordering and error handling.  Prints one JSON line per
 // scenario.
@@ -37,21 +37,6 @@ class FakeDevice : public tfs::DeviceOps {
         __atomic_store_n(&sh_.stop, 1, __ATOMIC_RELEASE);
         if (th_.joinable()) th_.join();
         return TF_OK;
-    }
-    int materialize(const tfs_desc &d, int *token) override {
-        std::lock_guard<std::mutex> g(mu_);
-        *token = next_token_++;
-        ready_at_[*token] = tfs::now_s() + 50e-6;
-        (void)d;
-        return TF_OK;
-    }
-    bool materialized(int token) override {
-        std::lock_guard<std::mutex> g(mu_);
-        return tfs::now_s() >= ready_at_[token];
-    }
-    void release_token(int token) override {
-        std::lock_guard<std::mutex> g(mu_);
-        ready_at_.erase(token);
     }
     int starts() const { return starts_; }
     std::set<int> slots_seen;
@@ -105,9 +90,6 @@ class FakeDevice : public tfs::DeviceOps {
     uint64_t process_us_;
     int idle_exit_ms_;
     int starts_ = 0;
-    std::mutex mu_;
-    int next_token_ = 0;
-    std::map<int, double> ready_at_;
 };
 
 static tfs_job make_job(int op, int dtype, int64_t n, int kind = TFS_KIND_RANDOM) {
