@@ -486,12 +486,25 @@ __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t 
         const int64_t first = b * span + (int64_t)wave * per_wave;
         const int64_t width = per_wave < 64 ? per_wave : 64;
         const int64_t chunks = per_wave / width;
-        for (int64_t j = 0; j < chunks; ++j) {
-            const int64_t i = first + j * width + lane;
-            Pair<T> v = (lane < width && i < count) ? in[i] : Pair<T>{T(0), T(0)};
-            v = butterfly_m<T, PLAIN>(v, lane, (int)width);
-            if (lane == j) mine = v;
-            if (chunks == 1) mine = v;
+        // Chunks of 64 partials, reduced in groups of kGroup whose loads are
+        // all issued before the first butterfly (one memory round trip per
+        // group instead of one per chunk); each chunk's tree is unchanged.
+        constexpr int kGroup = 16;
+        for (int64_t j0 = 0; j0 < chunks; j0 += kGroup) {
+            Pair<T> v[kGroup];
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                const int64_t i = first + (j0 + g) * width + lane;
+                v[g] = (j0 + g < chunks && lane < width && i < count) ? in[i] : Pair<T>{T(0), T(0)};
+            }
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                if (j0 + g < chunks) {
+                    const Pair<T> r = butterfly_m<T, PLAIN>(v[g], lane, (int)width);
+                    if (lane == j0 + g) mine = r;
+                    if (chunks == 1) mine = r;
+                }
+            }
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, (int)chunks);
     }
