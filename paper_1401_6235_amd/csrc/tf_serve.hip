@@ -451,8 +451,8 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
 #ifndef TF_SERVE_WORKERS_PER_CU
 #define TF_SERVE_WORKERS_PER_CU 1
 #endif
-#ifndef TF_SERVE_BATCH_SPLIT
-#define TF_SERVE_BATCH_SPLIT 1
+#ifndef TF_SERVE_BATCH_SHARE
+#define TF_SERVE_BATCH_SHARE 100  // percent of a fair share of the remaining units per claim
 #endif
 #ifndef TF_SERVE_IDLE_SLEEP
 #define TF_SERVE_IDLE_SLEEP 127  // s_sleep units (64 cycles) between scans of an idle worker
@@ -460,10 +460,10 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
 static_assert(TF_SERVE_WORKERS_PER_CU >= 1 && TF_SERVE_WORKERS_PER_CU <= 4, "1 to 4 worker blocks per CU");
 
 // Units per claim when `remaining` units of a job are left and `workers`
-// blocks compete: remaining / (split x workers), between 1 and
-// TFS_MAX_BATCH.
+// blocks compete: TF_SERVE_BATCH_SHARE percent of remaining / workers,
+// between 1 and TFS_MAX_BATCH.
 __device__ __forceinline__ uint64_t batch_for(uint64_t remaining, uint64_t workers) {
-    const uint64_t k = remaining / (TF_SERVE_BATCH_SPLIT * (workers ? workers : 1));
+    const uint64_t k = remaining * TF_SERVE_BATCH_SHARE / (100 * (workers ? workers : 1));
     return k < 1 ? 1 : k > TFS_MAX_BATCH ? TFS_MAX_BATCH : k;
 }
 
