@@ -351,6 +351,36 @@ def test_tight_budget_forces_waits():
     assert all(r["status"] == 0 for r in got.values())
 
 
+def test_progress_beside_other_streams():
+    """Jobs complete, bit for bit, while seven other streams of the process
+    have work queued: the persistent kernel depends on no other kernel (its
+    jobs' inputs are generated by its own workers), whichever hardware
+    queues the streams share."""
+    torch = torch_cuda()
+    streams = [torch.cuda.Stream() for _ in range(7)]
+    bufs = [torch.zeros(1 << 20, device="cuda") for _ in streams]
+    torch.cuda.synchronize()
+    jobs = random_jobs(40, 31, max_log2=16)
+    srv = S.Server(0, 1 << 30, 16)
+    try:
+        step("serve beside 7 busy streams")
+        ids = {}
+        for k, j in enumerate(jobs):
+            ids[srv.submit(make(j))] = j
+            with torch.cuda.stream(streams[k % 7]):
+                bufs[k % 7].add_(1.0)
+        got = wait_all(srv, len(jobs), timeout=60.0)
+    finally:
+        srv.close()
+    for s_ in streams:
+        s_.synchronize()
+    for k in range(7):
+        assert float(bufs[k][0]) == float(sum(1 for i in range(len(jobs)) if i % 7 == k))
+    for jid, r in got.items():
+        assert r["status"] == 0
+        check(r, expected(ids[jid]), "beside streams")
+
+
 def test_malformed_jobs_are_rejected():
     torch_cuda()
     srv = S.Server(0, 1 << 20, 4)
