@@ -495,8 +495,8 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                     s_slot = stop ? -3 : -1;
                 }
             } else if (key == m) {  // the one lane holding the chosen job
-                // Wait-free claim: the returned word names the unit this block
-                // owns.  The slot may have been emptied or reopened for a
+                // Wait-free claim: the returned word names the units this
+                // block owns and the phase they belong to.  The slot may have been emptied or reopened for a
                 // newer job since the scan; an add past the last unit (or on
                 // an empty word, which the next opening overwrites) claims
                 // nothing, and a unit of a newer job is as good as any.
@@ -508,9 +508,8 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
                 // on this chip, so the per-unit path keeps a single release.
                 // A large job is claimed a batch of consecutive units at a
                 // time (one fetch-add and one count per batch: atomics on
-                // one word serialise, at tens of nanoseconds each), sized
-                // so that the remaining units still split about twice over
-                // the workers.
+                // one word serialise, at tens of nanoseconds each), sized as
+                // a share of the remaining units per worker (batch_for).
                 const uint64_t k = batch_for(nt - nx, gridDim.x - 1);
                 const uint64_t old = __hip_atomic_fetch_add(&st->ctl[t], k, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
