@@ -433,7 +433,11 @@ class Server {
                 next_check = t + 1e-3;
                 const bool alive = dev_->running();
                 alive_ = alive;
-                if (!alive && running_) dev_->start();  // drained after an idle period: relaunch
+                // Drained after an idle period with jobs published (one can
+                // land just as the kernel exits): relaunch.  With nothing in
+                // flight it stays down until the next publish relaunches it,
+                // so other work of the process can use its hardware queue.
+                if (!alive && running_ && in_flight_.load() > 0) dev_->start();
             }
             if (progress) {
                 last_progress = t;

@@ -29,6 +29,7 @@ class FakeDevice : public tfs::DeviceOps {
         alive_ = true;
         starts_++;
         __atomic_store_n(&sh_.stop, 0, __ATOMIC_RELEASE);
+        __atomic_store_n(&sh_.kernel_state, 1, __ATOMIC_RELEASE);  // as the HIP backend: launched
         th_ = std::thread([this] { run(); });
         return TF_OK;
     }
@@ -51,6 +52,7 @@ class FakeDevice : public tfs::DeviceOps {
         uint64_t consumed = __atomic_load_n(&sh_.consumed, __ATOMIC_ACQUIRE);
         std::vector<Job> jobs;
         double last = tfs::now_s();
+        uint64_t how = 2;
         while (true) {
             const uint64_t pub = __atomic_load_n(&sh_.pub_count, __ATOMIC_ACQUIRE);
             while (consumed < pub) {
@@ -78,10 +80,17 @@ class FakeDevice : public tfs::DeviceOps {
                     ++k;
                 }
             }
-            if (__atomic_load_n(&sh_.stop, __ATOMIC_ACQUIRE) && jobs.empty()) break;
-            if (idle_exit_ms_ && jobs.empty() && tfs::now_s() - last > idle_exit_ms_ * 1e-3) break;
+            if (__atomic_load_n(&sh_.stop, __ATOMIC_ACQUIRE) && jobs.empty()) {
+                how = 2;
+                break;
+            }
+            if (idle_exit_ms_ && jobs.empty() && tfs::now_s() - last > idle_exit_ms_ * 1e-3) {
+                how = 3;
+                break;
+            }
             std::this_thread::sleep_for(std::chrono::microseconds(5));
         }
+        __atomic_store_n(&sh_.kernel_state, how, __ATOMIC_RELEASE);  // 2 stopped, 3 idle exit
         alive_ = false;
     }
     tfs_shared sh_;

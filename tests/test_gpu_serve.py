@@ -381,6 +381,25 @@ def test_progress_beside_other_streams():
         check(r, expected(ids[jid]), "beside streams")
 
 
+def test_relaunch_after_idle_drain():
+    """The persistent kernel drains after 20 ms without work and stays down
+    while nothing is in flight; the next job relaunches it and completes
+    with the oracle's result."""
+    torch_cuda()
+    jobs = random_jobs(6, 41, max_log2=14)
+    srv = S.Server(0, 1 << 28, 8)
+    try:
+        for k, j in enumerate(jobs):
+            step("serve after idle #%d" % k)
+            r = run_alone(srv, j)
+            assert r["status"] == 0
+            check(r, expected(j), "after idle")
+            time.sleep(0.1)  # > the idle drain
+            assert srv.stats()["kernel_alive"] == 0
+    finally:
+        srv.close()
+
+
 def test_malformed_jobs_are_rejected():
     torch_cuda()
     srv = S.Server(0, 1 << 20, 4)
