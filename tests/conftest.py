@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def _build_missing():
     """Build whatever native library is missing (never rebuilds a present
-    one: on a GPU machine the libraries built here travel with the tree)."""
+    one: the GPU tests use the libraries as built, wherever they run)."""
     import oracle
     from paper_1401_6235_amd import build as hipbuild
     from paper_1401_6235_amd import workloads
