@@ -52,6 +52,16 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int64_t count, 
     }
 }
 
+// The last level, one block: 16 waves share the join (a quarter of the
+// chunks per wave that four waves would fold one after another), same tree.
+constexpr int kWideBlock = 1024;
+template <typename T, bool PLAIN>
+__global__ __launch_bounds__(kWideBlock) void reduce_last_kernel(int64_t count, int64_t span, const Pair<T> *in,
+                                                                 T *out) {
+    const Pair<T> r = block_join<T, PLAIN, kWideBlock / 64>(0, count, span, in);
+    if (threadIdx.x == 0) write_out(out, r, PLAIN);
+}
+
 constexpr int64_t kMaxSpan = 4 * 64 * 64;  // partials one block joins
 
 static int64_t pow2_ceil(int64_t v) {
@@ -94,9 +104,12 @@ static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, 
         const int64_t next_count = (count + span - 1) / span;
         Pair<T> *dst = src + count;
         const bool last = next_padded == 1;
-        hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
-                           L.stream, count, span, (const Pair<T> *)src, dst,
-                           last ? out : (T *)nullptr);
+        if (last && span >= kWideBlock / 64)
+            hipLaunchKernelGGL((reduce_last_kernel<T, PLAIN>), dim3(1), dim3(kWideBlock), 0, L.stream, count, span,
+                               (const Pair<T> *)src, out);
+        else
+            hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
+                               L.stream, count, span, (const Pair<T> *)src, dst, last ? out : (T *)nullptr);
         src = dst;
         count = next_count;
         padded = next_padded;

@@ -389,18 +389,26 @@ __device__ __forceinline__ Pair<T> butterfly_m(Pair<T> v, int lane, int m) {
     return v;
 }
 
-// Join of the (at most 4) wave results of a block, in thread 0.
-template <typename T, bool PLAIN>
+// Join of the wave results of a block (`waves` a power of two, at most
+// MAXW): adjacent pairs, level by level, the same tree as the leaves'.
+template <typename T, bool PLAIN, int MAXW = 4>
 __device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
-    __shared__ Pair<T> wres[4];
+    __shared__ Pair<T> wres[MAXW];
     const int wave = threadIdx.x >> 6;
     if (wave < waves && (threadIdx.x & 63) == 0) wres[wave] = mine;
     __syncthreads();
-    Pair<T> r = wres[0];
-    if (waves == 2) r = node<T, PLAIN>(wres[0], wres[1]);
-    if (waves == 4) r = node<T, PLAIN>(node<T, PLAIN>(wres[0], wres[1]), node<T, PLAIN>(wres[2], wres[3]));
+    Pair<T> v[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) v[k] = k < waves ? wres[k] : Pair<T>{T(0), T(0)};
+#pragma unroll
+    for (int w = MAXW; w > 1; w >>= 1) {
+        if (w <= waves) {
+#pragma unroll
+            for (int k = 0; k < w / 2; ++k) v[k] = node<T, PLAIN>(v[2 * k], v[2 * k + 1]);
+        }
+    }
     __syncthreads();
-    return r;
+    return v[0];
 }
 
 // Value of the aligned subtree of `per_block` tiles (a power of two, at most
@@ -472,14 +480,14 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
 }
 
 // Join of the aligned group of `span` partials (a power of two, at most
-// 4 * 64 * 64) starting at b * span; partials at index >= count are
-// (+0, +0).  Each wave folds span / 4 consecutive partials (or one) in
-// chunks of 64 lanes, lane j keeping chunk j; valid in thread 0.  Call from
-// every thread.
-template <typename T, bool PLAIN>
+// WAVES * 64 * 64) starting at b * span; partials at index >= count are
+// (+0, +0).  Each of the block's WAVES waves folds span / WAVES consecutive
+// partials (or one) in chunks of 64 lanes, lane j keeping chunk j; the tree
+// is the same for any WAVES.  Valid in thread 0.  Call from every thread.
+template <typename T, bool PLAIN, int WAVES = 4>
 __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t span, const Pair<T> *in) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t per_wave = span >= 4 ? span / 4 : 1;
+    const int64_t per_wave = span >= WAVES ? span / WAVES : 1;
     const int waves = (int)(span / per_wave);
     Pair<T> mine{T(0), T(0)};
     if (wave < waves) {
@@ -489,7 +497,7 @@ __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t 
         // Chunks of 64 partials, reduced in groups of kGroup whose loads are
         // all issued before the first butterfly (one memory round trip per
         // group instead of one per chunk); each chunk's tree is unchanged.
-        constexpr int kGroup = 16;
+        constexpr int kGroup = 64 / WAVES;  // 16 chunks per group with 4 waves, 4 with 16
         for (int64_t j0 = 0; j0 < chunks; j0 += kGroup) {
             Pair<T> v[kGroup];
 #pragma unroll
@@ -508,7 +516,7 @@ __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t 
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, (int)chunks);
     }
-    return join_waves<T, PLAIN>(mine, waves);
+    return join_waves<T, PLAIN, WAVES>(mine, waves);
 }
 
 }  // namespace tf
