@@ -19,7 +19,7 @@
 // release).  Workers never wait for each other, so the grid needs no
 // co-residency; every wave leaves its loop once the dispatcher has raised
 // the stop flag and no unit is left, and the dispatcher itself exits on the
-// host's stop request or after a long idle period.
+// host's stop request or after 20 ms without work.
 //
 // Inputs of RANDOM / ILLCOND jobs are written by the workers themselves, in
 // a generation phase of the job that precedes its compute units (the
