@@ -392,7 +392,9 @@ template <typename T>
 __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done *rec) {
     tfs_done out = {};
     if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
-        const Pair<T> r = block_join<T, false>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
+        // four chunks in flight: the serving kernel's register budget is set
+        // by its largest path, and two waves per SIMD must fit
+        const Pair<T> r = block_join<T, false, 4, 4>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
         const double z0 = (double)r.hi, z1 = (double)r.lo;
         out.z0 = z0;
         out.z1 = z1;
@@ -621,8 +623,13 @@ class HipDevice : public tfs::DeviceOps {
         (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
         tick_hz_ = (double)rate_khz * 1000.0;
-        // at most 1024 workers: the claim counter's overshoot bound
-        workers_ = cus * TF_SERVE_WORKERS_PER_CU;
+        // The grid (dispatcher + workers) is exactly TF_SERVE_WORKERS_PER_CU
+        // blocks per CU, so every block is resident whatever the kernel's
+        // register count (a block left waiting for a CU would never run
+        // beside the persistent ones); at most 1024 workers: the claim
+        // counter's overshoot bound.
+        workers_ = cus * TF_SERVE_WORKERS_PER_CU - 1;
+        if (workers_ < 1) workers_ = 1;
         if (workers_ > 1024) workers_ = 1024;
         return TF_OK;
     }

@@ -482,9 +482,10 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
 // Join of the aligned group of `span` partials (a power of two, at most
 // WAVES * 64 * 64) starting at b * span; partials at index >= count are
 // (+0, +0).  Each of the block's WAVES waves folds span / WAVES consecutive
-// partials (or one) in chunks of 64 lanes, lane j keeping chunk j; the tree
-// is the same for any WAVES.  Valid in thread 0.  Call from every thread.
-template <typename T, bool PLAIN, int WAVES = 4>
+// partials (or one) in chunks of 64 lanes, lane j keeping chunk j, GROUP
+// chunks' loads at a time; the tree is the same for any WAVES and GROUP.
+// Valid in thread 0.  Call from every thread.
+template <typename T, bool PLAIN, int WAVES = 4, int GROUP = 64 / WAVES>
 __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t span, const Pair<T> *in) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t per_wave = span >= WAVES ? span / WAVES : 1;
@@ -497,7 +498,7 @@ __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t 
         // Chunks of 64 partials, reduced in groups of kGroup whose loads are
         // all issued before the first butterfly (one memory round trip per
         // group instead of one per chunk); each chunk's tree is unchanged.
-        constexpr int kGroup = 64 / WAVES;  // 16 chunks per group with 4 waves, 4 with 16
+        constexpr int kGroup = GROUP;  // chunks whose loads are in flight together
         for (int64_t j0 = 0; j0 < chunks; j0 += kGroup) {
             Pair<T> v[kGroup];
 #pragma unroll
