@@ -321,29 +321,57 @@ template void run_plain_quadratic<float>(const Launch &, int64_t, const void *, 
 
 // ---- fma ------------------------------------------------------------------------
 
+#ifndef TF_FMA_UNROLL_F64
+#define TF_FMA_UNROLL_F64 4
+#endif
+#ifndef TF_FMA_UNROLL_F32
+#define TF_FMA_UNROLL_F32 4
+#endif
+template <typename T>
+struct FmaUnroll {
+    static constexpr int U = sizeof(T) == 8 ? TF_FMA_UNROLL_F64 : TF_FMA_UNROLL_F32;
+};
+
+// U 16-byte vectors per operand and thread, consecutive threads on
+// consecutive vectors within each of the U strips of the block.
 template <typename T, bool XT, bool YT, bool WT>
 __global__ __launch_bounds__(kBlock) void fma_vec_kernel(int64_t n, const T *x0, const T *x1, const T *y0,
                                                          const T *y1, const T *w0, const T *w1, T *z0, T *z1) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
+    constexpr int U = FmaUnroll<T>::U;
     const int64_t nvec = n / W;
-    const int64_t step = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nvec; i += step) {
-        const V p0 = vload(x0, i), q0 = vload(y0, i), s0 = vload(w0, i);
-        V p1, q1, s1;
-        if constexpr (XT) p1 = vload(x1, i);
-        if constexpr (YT) q1 = vload(y1, i);
-        if constexpr (WT) s1 = vload(w1, i);
-        V r0, r1;
+    const int64_t step = (int64_t)gridDim.x * kBlock * U;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock * U + threadIdx.x; base < nvec; base += step) {
+        V p0[U], q0[U], s0[U], p1[U], q1[U], s1[U];
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const Pair<T> z = fma_t<T, XT, YT, WT>(p0[k], XT ? p1[k] : T(0), q0[k], YT ? q1[k] : T(0), s0[k],
-                                                   WT ? s1[k] : T(0));
-            r0[k] = z.hi;
-            r1[k] = z.lo;
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + (int64_t)u * kBlock;
+            if (i < nvec) {
+                p0[u] = vload(x0, i);
+                q0[u] = vload(y0, i);
+                s0[u] = vload(w0, i);
+                if constexpr (XT) p1[u] = vload(x1, i);
+                if constexpr (YT) q1[u] = vload(y1, i);
+                if constexpr (WT) s1[u] = vload(w1, i);
+            }
         }
-        vstore(z0, i, r0);
-        vstore(z1, i, r1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + (int64_t)u * kBlock;
+            if (i < nvec) {
+                V r0, r1;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const Pair<T> z = fma_t<T, XT, YT, WT>(p0[u][k], XT ? p1[u][k] : T(0), q0[u][k],
+                                                           YT ? q1[u][k] : T(0), s0[u][k], WT ? s1[u][k] : T(0));
+                    r0[k] = z.hi;
+                    r1[k] = z.lo;
+                }
+                vstore(z0, i, r0);
+                vstore(z1, i, r1);
+            }
+        }
     }
     if (blockIdx.x == 0) {
         const int64_t i = nvec * W + threadIdx.x;
@@ -372,7 +400,8 @@ __global__ __launch_bounds__(kBlock) void fma_scalar_kernel(int64_t n, const T *
 template <typename T, bool XT, bool YT, bool WT>
 static void launch_fma(const Launch &L, int64_t n, const T *const *p, T *z0, T *z1) {
     if (L.aligned)
-        hipLaunchKernelGGL((fma_vec_kernel<T, XT, YT, WT>), dim3(grid_for(n / Vec<T>::N, kBlock, L.cap)),
+        hipLaunchKernelGGL((fma_vec_kernel<T, XT, YT, WT>),
+                           dim3(grid_for((n / Vec<T>::N + FmaUnroll<T>::U - 1) / FmaUnroll<T>::U, kBlock, L.cap)),
                            dim3(kBlock), 0, L.stream, n, p[0], p[1], p[2], p[3], p[4], p[5], z0, z1);
     else
         hipLaunchKernelGGL((fma_scalar_kernel<T, XT, YT, WT>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0,
