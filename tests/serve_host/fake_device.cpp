@@ -140,7 +140,7 @@ static int run_stream(uint64_t budget, int slots, int count, uint64_t process_us
         if (st != TF_OK) return 2;
         sent[id] = j;
         order.push_back(id);
-        if (idle_exit_ms && k == count / 2) std::this_thread::sleep_for(std::chrono::milliseconds(3 * idle_exit_ms));
+        if (idle_exit_ms && k == count / 2) std::this_thread::sleep_for(std::chrono::milliseconds(10 * idle_exit_ms));
     }
     std::vector<tfs_result> got;
     const double t0 = tfs::now_s();

@@ -48,7 +48,11 @@ def check(res):
     assert res["tight_budget"]["waits"] > 0          # the budget forced the queue head to wait
     assert res["two_slots"]["max_in_flight"] <= 2     # slots bound the jobs in flight
     assert res["stream"]["max_in_flight"] > 8         # continuous batching: many jobs at once
-    assert res["device_restart"]["starts"] >= 2       # a drained worker is relaunched
+    # a drained worker is relaunched by the next publish, and not before:
+    # with nothing in flight it stays down through the 200 ms pause (ten
+    # idle periods; relaunching on every drain would start it ~10 times),
+    # so other work can use its hardware queue
+    assert 2 <= res["device_restart"]["starts"] <= 3
 
 
 def test_server_host_logic(tmp_path):
