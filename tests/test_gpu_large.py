@@ -1,5 +1,6 @@
-"""GPU parity past 2^31 elements: 64-bit indexing in the elementwise and
-reduction kernels and the multi-level partial join at that size.
+"""GPU parity past 2^31 elements, binary32 and binary64: 64-bit indexing in
+the elementwise and reduction kernels and the multi-level partial join at
+that size.
 
 Inputs are seeded on the device with torch's generator (sign-uniform high
 parts in [0.5, 1.5), low parts about one unit in the last place); the
@@ -20,21 +21,23 @@ from gpu_util import assert_bits, step, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-N_BIG = (1 << 31) + 1000003  # float32: 8 GiB per array
+N_BIG = (1 << 31) + 1000003  # 8 GiB per binary32 array, 16 GiB per binary64 array
+GIB = 1 << 30
 
 
-def _operands(torch, n, seed, with_y=True):
+def _operands(torch, n, seed, dtype, with_y=True):
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    f32 = torch.float32
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    ulp = 2.0 ** -24 if dtype == "f32" else 2.0 ** -53
 
     def hi():
-        v = torch.rand(n, generator=g, device="cuda", dtype=f32) + 0.5
+        v = torch.rand(n, generator=g, device="cuda", dtype=dt) + 0.5
         sign = torch.randint(0, 2, (n,), generator=g, device="cuda", dtype=torch.int8)
         return torch.where(sign == 1, -v, v)
 
     def lo(h):
-        return h * ((torch.rand(n, generator=g, device="cuda", dtype=f32) * 2 - 1) * 2.0 ** -24)
+        return h * ((torch.rand(n, generator=g, device="cuda", dtype=dt) * 2 - 1) * ulp)
 
     x0 = hi()
     x1 = lo(x0)
@@ -50,13 +53,15 @@ def _sample_indices(n, rng):
     return np.unique(np.concatenate([np.array(edge, np.int64), rng.integers(0, n, 4096)]))
 
 
-def test_add_past_2e31_elements():
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_add_past_2e31_elements(dtype):
     torch = torch_cuda()
     free, _ = torch.cuda.mem_get_info()
-    if free < 60 << 30:
-        pytest.skip("needs about 60 GiB of free device memory")
-    step("twofold add float32 n = 2^31 + 1000003")
-    x0, x1, y0, y1 = _operands(torch, N_BIG, 20)
+    need = (60 if dtype == "f32" else 120) * GIB
+    if free < need:
+        pytest.skip("needs about %d GiB of free device memory" % (need // GIB))
+    step("twofold add %s n = 2^31 + 1000003" % dtype)
+    x0, x1, y0, y1 = _operands(torch, N_BIG, 20, dtype)
     z0, z1 = tf.tf_add(x0, x1, y0, y1)
     torch.cuda.synchronize()
     idx = _sample_indices(N_BIG, np.random.default_rng(3))
@@ -69,13 +74,15 @@ def test_add_past_2e31_elements():
     assert_bits(host[5], want[1], "z1")
 
 
-def test_sum_past_2e31_elements():
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sum_past_2e31_elements(dtype):
     torch = torch_cuda()
     free, _ = torch.cuda.mem_get_info()
-    if free < 40 << 30:
-        pytest.skip("needs about 40 GiB of free device memory")
-    step("twofold sum float32 n = 2^31 + 1000003")
-    x0, x1, _, _ = _operands(torch, N_BIG, 21, with_y=False)
+    need = (40 if dtype == "f32" else 80) * GIB
+    if free < need:
+        pytest.skip("needs about %d GiB of free device memory" % (need // GIB))
+    step("twofold sum %s n = 2^31 + 1000003" % dtype)
+    x0, x1, _, _ = _operands(torch, N_BIG, 21, dtype, with_y=False)
     whole = tf.tf_sum(x0, x1).cpu().numpy()
     half = 1 << 31
     left = tf.tf_sum(x0[:half], x1[:half]).cpu().numpy()
