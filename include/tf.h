@@ -341,7 +341,7 @@ typedef struct {
     int dtype;     /* TF_F32 / TF_F64 */
     int kind;      /* TFS_KIND_* */
     int degree;    /* Horner degree, 0 .. TF_MAX_DEGREE */
-    int64_t n;     /* 1 .. 16384 * 4095 elements */
+    int64_t n;     /* 1 .. 4096 * 16383 elements (16383 units of 4096) */
     uint64_t seed; /* input generator seed (RANDOM, ILLCOND) */
     double a[2];   /* axpy twofold scalar (rounded to dtype) */
     double c[TF_MAX_DEGREE + 1]; /* Horner coefficients (rounded to dtype) */

@@ -11,6 +11,7 @@ import ctypes as C
 from . import TF_F32, TF_F64, TF_MAX_DEGREE, TwofoldError, lib
 
 TFS_MAX_SLOTS = 64
+TFS_MAX_N = 4096 * 16383  # elements per job: 16383 units of 4096
 TFS_OP_SUM, TFS_OP_DOT, TFS_OP_AXPY, TFS_OP_HORNER = 0, 1, 2, 3
 TFS_KIND_RANDOM, TFS_KIND_ILLCOND, TFS_KIND_PROVIDED = 0, 1, 2
 OPS = {"sum": TFS_OP_SUM, "dot": TFS_OP_DOT, "axpy": TFS_OP_AXPY, "horner": TFS_OP_HORNER}

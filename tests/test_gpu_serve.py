@@ -400,6 +400,26 @@ def test_relaunch_after_idle_drain():
         srv.close()
 
 
+@pytest.mark.parametrize("op", ["sum", "axpy"])
+def test_largest_jobs(op):
+    """Jobs of the largest accepted length, 16383 units of 4096 elements:
+    the unit count fills its 14-bit field and batched claims run up to it,
+    bit for bit against the oracle; one element more is rejected."""
+    torch_cuda()
+    srv = S.Server(0, 8 << 30, 4)
+    try:
+        job = {"op": op, "dtype": "f64", "n": S.TFS_MAX_N, "seed": 99, "illcond": False,
+               "c": [0.5] * 9}
+        step("serve largest job %s n = %d" % (op, S.TFS_MAX_N))
+        r = run_alone(srv, job)
+        assert r["status"] == 0
+        check(r, expected(job), "largest %s" % op)
+        with pytest.raises(Exception):
+            srv.submit(S.make_job(op, "f64", S.TFS_MAX_N + 1))
+    finally:
+        srv.close()
+
+
 def test_malformed_jobs_are_rejected():
     torch_cuda()
     srv = S.Server(0, 1 << 20, 4)
