@@ -50,6 +50,11 @@
 #define TFS_CTL_PHASE(c) (((c) >> 31) & 1u)
 #define TFS_CTL_NTILES(c) (((c) >> 17) & 0x3fffu)
 #define TFS_CTL_NEXT(c) ((c)&0x1ffffu)
+#ifdef __cplusplus
+static_assert(TFS_MAX_CLAIMS <= 0x3fff, "unit count fits its 14-bit field");
+static_assert(TFS_MAX_CLAIMS + TFS_MAX_BATCH * 1024 <= 0x1ffff,
+              "next unit plus the overshoot of 1024 workers fits its 17-bit field");
+#endif
 
 typedef struct {
     uint64_t gen;      /* publication number, 1, 2, ... */
