@@ -56,6 +56,7 @@ def _sample_indices(n, rng):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_add_past_2e31_elements(dtype):
     torch = torch_cuda()
+    torch.cuda.empty_cache()  # memory cached by earlier tests
     free, _ = torch.cuda.mem_get_info()
     need = (60 if dtype == "f32" else 120) * GIB
     if free < need:
@@ -77,6 +78,7 @@ def test_add_past_2e31_elements(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_sum_past_2e31_elements(dtype):
     torch = torch_cuda()
+    torch.cuda.empty_cache()  # memory cached by earlier tests
     free, _ = torch.cuda.mem_get_info()
     need = (40 if dtype == "f32" else 80) * GIB
     if free < need:
