@@ -108,6 +108,27 @@ def test_mul_and_div_with_dotted_divisor(dtype):
         assert abs(F(z1[i]) - dz0) <= gamma(2, dtype) * abs(dz0)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_div_with_dotted_dividend(dtype):
+    """Dotted x over twofold y is DTF1 with x1 = +0 (the overload set lists it
+    without a formula): the DTF1 bound with x1 = 0 against the exact dz0.
+    A form that ignores y1 is off by about |z0 y1 / y0|, far outside it."""
+    x0, _, y0, y1 = _cases(dtype, 23)
+    y1 = np.where(np.abs(y1) > 0.25 * np.abs(y0), y1 * np.asarray(0.125, dtype), y1).astype(dtype)
+    z0, z1 = oracle.div(x0, None, y0, y1)
+    zero = np.zeros(1, dtype)[0]
+    worst = Fraction(0)
+    for i in range(N):
+        assert z0[i] == x0[i] / y0[i]
+        dz0 = exact_dz0("div", x0[i], zero, y0[i], y1[i], z0[i])
+        b = bound_div(x0[i], zero, y0[i], y1[i], z0[i], dz0, dtype)
+        err = abs(F(z1[i]) - dz0)
+        assert err <= b, i
+        if b:
+            worst = max(worst, err / b)
+    assert worst > 0
+
+
 def _mp(v):
     return mpmath.mpf(float(v))
 

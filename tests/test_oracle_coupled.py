@@ -135,6 +135,26 @@ def test_dpf1_exact_cases(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_dpf1_dotted_dividend_exact_cases(dtype):
+    """A dotted dividend over a coupled divisor is DPF1 with x1 = +0, so on
+    exact cases z1 = -z0 y1 / y0 exactly (zero if y1 were dropped)."""
+    g = np.random.default_rng(50)
+    n = N
+    q = g.integers(-40, 41, n)
+    q[q == 0] = 1
+    k = g.integers(-4, 5, n)
+    sh = 20 if np.dtype(dtype) == np.float64 else 8
+    y0 = np.exp2(k).astype(dtype)
+    x0 = (q * np.exp2(k)).astype(dtype)
+    y1 = (g.integers(-63, 64, n) * np.exp2(k - sh)).astype(dtype)
+    y1[y1 == 0] = np.exp2(k[y1 == 0] - sh).astype(dtype)
+    z0, z1 = oracle.coupled("div", x0, None, y0, y1)
+    for i in range(n):
+        assert F(z0[i]) == q[i]
+        assert F(z1[i]) == -F(z0[i]) * F(y1[i]) / F(y0[i]), i
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_dpf1_bound_on_coupled_operands(dtype):
     x0, x1 = coupled_operands(dtype, N, 51)
     y0, y1 = coupled_operands(dtype, N, 52)

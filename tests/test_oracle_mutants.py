@@ -117,6 +117,14 @@ MUTANTS = [
      "z.z1 = c0 / y0;\n    return z;\n}\n\n/* One coupled",
      "z.z1 = c0 / (y0 + y1);\n    return z;\n}\n\n/* One coupled",
      [lambda: CP.test_dpf1_exact_cases(F64)]),
+    ("dtf1_dotted_dividend_drops_y1",
+     "return NM(div_tt)(x0, (T)0, y0, y1);",
+     "return NM(div_tt)(x0, (T)0, y0, (T)0);",
+     [lambda: B.test_div_with_dotted_dividend(F64), lambda: P.test_dtf1_example_with_dotted_dividend(F64)]),
+    ("dpf1_dotted_dividend_drops_y1",
+     ": yt ? NM(div_pp)(x0, (T)0, y0, y1)",
+     ": yt ? NM(div_pp)(x0, (T)0, y0, (T)0)",
+     [lambda: CP.test_dpf1_dotted_dividend_exact_cases(F64)]),
     ("dpf1_r1_sign",
      "T r1 = FMA(-z0, y1, x1);\n    T c0 = r0 + r1;\n    PAIR z;",
      "T r1 = FMA(z0, y1, x1);\n    T c0 = r0 + r1;\n    PAIR z;",

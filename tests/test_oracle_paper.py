@@ -177,3 +177,16 @@ def test_quadratic_log(run):
         p0, p1 = parse(run[name])
         assert close6(got[0], p0), (name, got)
         assert close6(got[1], sign * p1), (name, got)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_dtf1_example_with_dotted_dividend(dtype):
+    """The Divide example's dividend is the plain 1, so the dotted-dividend
+    form (DTF1 with x1 = +0) must give the printed z0 = 1 + 2 eps and
+    z1 = -2 eps too; dropping y1 gives z1 close to -eps instead."""
+    ex = next(e for e in EXAMPLES["examples"] if e["name"] == "dtf1_example")
+    x0 = expand(ex["x"][0], dtype)
+    y0, y1 = (expand(c, dtype) for c in ex["y"])
+    z0, z1 = oracle.div(one(x0, dtype), None, one(y0, dtype), one(y1, dtype))
+    assert z0[0] == expand(ex["z"][0], dtype)
+    assert z1[0] == expand(ex["z"][1], dtype)
