@@ -12,6 +12,7 @@ nothing here falls back to any other implementation.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -99,8 +100,23 @@ def _host_array(values, code):
     return t, C.c_void_p(t.data_ptr())
 
 
-def _out(z, like):
-    return _torch().empty_like(like) if z is None else z
+def _on(stream):
+    """Context for buffers made here: allocated on the stream whose kernels
+    use them, so torch's caching allocator cannot hand their memory to other
+    work while those kernels may still read or write it."""
+    return contextlib.nullcontext() if stream is None else _torch().cuda.stream(stream)
+
+
+def _out(z, like, stream=None):
+    if z is not None:
+        return z
+    with _on(stream):
+        return _torch().empty_like(like)
+
+
+def _empty(count, like, stream=None):
+    with _on(stream):
+        return _torch().empty(count, dtype=like.dtype, device=like.device)
 
 
 # ---------------------------------------------------------------------------
@@ -110,7 +126,7 @@ def _out(z, like):
 def _binary(name, x0, x1, y0, y1, z0, z1, stream):
     n = x0.numel()
     code = _dtype_code(x0)
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = getattr(lib(), name)(C.c_int(code), C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype),
                               _ptr(y0, n, x0.dtype), _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype),
                               _ptr(z1, n, x0.dtype), _stream(stream))
@@ -141,7 +157,7 @@ def tf_div(x0, x1, y0, y1, z0=None, z1=None, stream=None):
 def tf_sqrt(x0, x1, z0=None, z1=None, stream=None):
     """Twofold square root (RTF1 / RPF1.1)."""
     n = x0.numel()
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_sqrt(C.c_int(_dtype_code(x0)), C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype),
                        _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype), _stream(stream))
     _check(st, "tf_sqrt")
@@ -153,7 +169,7 @@ def tf_axpy(a, x0, x1, y0, y1, z0=None, z1=None, stream=None):
     n = x0.numel()
     code = _dtype_code(x0)
     ha, pa = _host_array(a, code)
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_axpy(C.c_int(code), C.c_int64(n), pa, _ptr(x0, n), _ptr(x1, n, x0.dtype),
                        _ptr(y0, n, x0.dtype), _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype),
                        _ptr(z1, n, x0.dtype), _stream(stream))
@@ -166,7 +182,7 @@ def tf_horner(c, x0, x1, z0=None, z1=None, stream=None):
     n = x0.numel()
     code = _dtype_code(x0)
     hc, pc = _host_array(c, code)
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_horner(C.c_int(code), C.c_int64(n), C.c_int(hc.numel() - 1), pc, _ptr(x0, n),
                          _ptr(x1, n, x0.dtype), _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype),
                          _stream(stream))
@@ -182,19 +198,22 @@ def tf_reduce_workspace_bytes(dtype_code: int, n: int) -> int:
     return int(lib().tf_reduce_workspace_bytes(dtype_code, n))
 
 
-def workspace(x0, n=None):
-    """A workspace tensor large enough for a reduction over x0."""
+def workspace(x0, n=None, stream=None):
+    """A workspace tensor large enough for a reduction over x0, allocated on
+    ``stream`` (default: the current stream), the stream the reduction that
+    uses it must run on."""
     torch = _torch()
     n = x0.numel() if n is None else n
     b = tf_reduce_workspace_bytes(_dtype_code(x0), n)
-    return torch.empty(max(b, 1), dtype=torch.uint8, device=x0.device)
+    with _on(stream):
+        return torch.empty(max(b, 1), dtype=torch.uint8, device=x0.device)
 
 
 def tf_sum(x0, x1=None, out=None, work=None, stream=None):
     """Twofold sum; returns a 2-element device tensor (z0, z1)."""
     n = x0.numel()
-    out = _torch().empty(2, dtype=x0.dtype, device=x0.device) if out is None else out
-    work = workspace(x0) if work is None else work
+    out = _empty(2, x0, stream) if out is None else out
+    work = workspace(x0, stream=stream) if work is None else work
     st = lib().tf_sum(C.c_int(_dtype_code(x0)), C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype),
                       _ptr(out, 2, x0.dtype), _ptr(work), C.c_size_t(work.numel() * work.element_size()),
                       _stream(stream))
@@ -205,8 +224,8 @@ def tf_sum(x0, x1=None, out=None, work=None, stream=None):
 def tf_dot(x0, x1, y0, y1, out=None, work=None, stream=None):
     """Twofold dot product; returns a 2-element device tensor (z0, z1)."""
     n = x0.numel()
-    out = _torch().empty(2, dtype=x0.dtype, device=x0.device) if out is None else out
-    work = workspace(x0) if work is None else work
+    out = _empty(2, x0, stream) if out is None else out
+    work = workspace(x0, stream=stream) if work is None else work
     st = lib().tf_dot(C.c_int(_dtype_code(x0)), C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype),
                       _ptr(y0, n, x0.dtype), _ptr(y1, n, x0.dtype), _ptr(out, 2, x0.dtype), _ptr(work),
                       C.c_size_t(work.numel() * work.element_size()), _stream(stream))
@@ -220,7 +239,7 @@ def tf_dot(x0, x1, y0, y1, out=None, work=None, stream=None):
 
 def _plain2(name, x, y, z, stream):
     n = x.numel()
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = getattr(lib(), name)(C.c_int(_dtype_code(x)), C.c_int64(n), _ptr(x, n), _ptr(y, n, x.dtype),
                               _ptr(z, n, x.dtype), _stream(stream))
     _check(st, name)
@@ -249,7 +268,7 @@ def tf_vmem(x, y, z=None, stream=None):
 
 def tf_plain_sqrt(x, z=None, stream=None):
     n = x.numel()
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = lib().tf_plain_sqrt(C.c_int(_dtype_code(x)), C.c_int64(n), _ptr(x, n), _ptr(z, n, x.dtype),
                              _stream(stream))
     _check(st, "tf_plain_sqrt")
@@ -260,7 +279,7 @@ def tf_plain_axpy(a0, x, y, z=None, stream=None):
     n = x.numel()
     code = _dtype_code(x)
     ha, pa = _host_array([a0], code)
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = lib().tf_plain_axpy(C.c_int(code), C.c_int64(n), pa, _ptr(x, n), _ptr(y, n, x.dtype),
                              _ptr(z, n, x.dtype), _stream(stream))
     _check(st, "tf_plain_axpy")
@@ -271,7 +290,7 @@ def tf_plain_horner(c, x, z=None, stream=None):
     n = x.numel()
     code = _dtype_code(x)
     hc, pc = _host_array(c, code)
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = lib().tf_plain_horner(C.c_int(code), C.c_int64(n), C.c_int(hc.numel() - 1), pc, _ptr(x, n),
                                _ptr(z, n, x.dtype), _stream(stream))
     _check(st, "tf_plain_horner")
@@ -280,8 +299,8 @@ def tf_plain_horner(c, x, z=None, stream=None):
 
 def tf_plain_sum(x, out=None, work=None, stream=None):
     n = x.numel()
-    out = _torch().empty(1, dtype=x.dtype, device=x.device) if out is None else out
-    work = workspace(x) if work is None else work
+    out = _empty(1, x, stream) if out is None else out
+    work = workspace(x, stream=stream) if work is None else work
     st = lib().tf_plain_sum(C.c_int(_dtype_code(x)), C.c_int64(n), _ptr(x, n), _ptr(out, 1, x.dtype),
                             _ptr(work), C.c_size_t(work.numel() * work.element_size()), _stream(stream))
     _check(st, "tf_plain_sum")
@@ -290,8 +309,8 @@ def tf_plain_sum(x, out=None, work=None, stream=None):
 
 def tf_plain_dot(x, y, out=None, work=None, stream=None):
     n = x.numel()
-    out = _torch().empty(1, dtype=x.dtype, device=x.device) if out is None else out
-    work = workspace(x) if work is None else work
+    out = _empty(1, x, stream) if out is None else out
+    work = workspace(x, stream=stream) if work is None else work
     st = lib().tf_plain_dot(C.c_int(_dtype_code(x)), C.c_int64(n), _ptr(x, n), _ptr(y, n, x.dtype),
                             _ptr(out, 1, x.dtype), _ptr(work), C.c_size_t(work.numel() * work.element_size()),
                             _stream(stream))
@@ -316,7 +335,7 @@ def tf_coupled(op, x0, x1, y0=None, y1=None, renorm=False, z0=None, z1=None, str
     """Coupled operation (ATF1, STF1, MPF1, DPF1, RPF1); ``renorm`` adds Fast
     Two-Sum (Dekker mode).  ``op`` is "add", "sub", "mul", "div" or "sqrt"."""
     n = x0.numel()
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_coupled(C.c_int(_dtype_code(x0)), C.c_int(TF_OPS[op]), C.c_int(int(bool(renorm))),
                           C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype), _ptr(y0, n, x0.dtype),
                           _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype), _stream(stream))
@@ -327,7 +346,7 @@ def tf_coupled(op, x0, x1, y0=None, y1=None, renorm=False, z0=None, z1=None, str
 def tf_renorm(z0, z1, s=None, t=None, stream=None):
     """Fast Two-Sum renormalisation of each twofold."""
     n = z0.numel()
-    s, t = _out(s, z0), _out(t, z0)
+    s, t = _out(s, z0, stream), _out(t, z0, stream)
     st = lib().tf_renorm(C.c_int(_dtype_code(z0)), C.c_int64(n), _ptr(z0, n), _ptr(z1, n, z0.dtype),
                          _ptr(s, n, z0.dtype), _ptr(t, n, z0.dtype), _stream(stream))
     _check(st, "tf_renorm")
@@ -338,7 +357,7 @@ def tf_chain(op, mode, reps, x0, x1, y0=None, y1=None, z0=None, z1=None, stream=
     """z = (x0, x1 or +0), then ``reps`` times z = z op y (sqrt: sqrt(z)),
     in registers; ``mode`` is "twofold", "coupled" or "dekker"."""
     n = x0.numel()
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_chain(C.c_int(_dtype_code(x0)), C.c_int(TF_OPS[op]), C.c_int(TF_MODES[mode]), C.c_int64(n),
                         C.c_int64(reps), _ptr(x0, n), _ptr(x1, n, x0.dtype), _ptr(y0, n, x0.dtype),
                         _ptr(y1, n, x0.dtype), _ptr(z0, n, x0.dtype), _ptr(z1, n, x0.dtype), _stream(stream))
@@ -348,7 +367,7 @@ def tf_chain(op, mode, reps, x0, x1, y0=None, y1=None, z0=None, z1=None, stream=
 
 def tf_plain_chain(op, reps, x, y=None, z=None, stream=None):
     n = x.numel()
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = lib().tf_plain_chain(C.c_int(_dtype_code(x)), C.c_int(TF_OPS[op]), C.c_int64(n), C.c_int64(reps),
                               _ptr(x, n), _ptr(y, n, x.dtype), _ptr(z, n, x.dtype), _stream(stream))
     _check(st, "tf_plain_chain")
@@ -363,7 +382,7 @@ def tf_trsv_upper(m, U0, U1, f0, f1=None, x0=None, x1=None, stream=None):
     """Back-substitution of upper-triangular m x m systems, interleaved:
     U[(i*m + j)*nsys + k], f and x [i*nsys + k]."""
     nsys = f0.numel() // m
-    x0, x1 = _out(x0, f0), _out(x1, f0)
+    x0, x1 = _out(x0, f0, stream), _out(x1, f0, stream)
     st = lib().tf_trsv_upper(C.c_int(_dtype_code(f0)), C.c_int64(nsys), C.c_int(m),
                              _ptr(U0, m * m * nsys, f0.dtype), _ptr(U1, m * m * nsys, f0.dtype),
                              _ptr(f0, m * nsys), _ptr(f1, m * nsys, f0.dtype), _ptr(x0, m * nsys, f0.dtype),
@@ -374,7 +393,7 @@ def tf_trsv_upper(m, U0, U1, f0, f1=None, x0=None, x1=None, stream=None):
 
 def tf_plain_trsv_upper(m, U, f, x=None, stream=None):
     nsys = f.numel() // m
-    x = _out(x, f)
+    x = _out(x, f, stream)
     st = lib().tf_plain_trsv_upper(C.c_int(_dtype_code(f)), C.c_int64(nsys), C.c_int(m),
                                    _ptr(U, m * m * nsys, f.dtype), _ptr(f, m * nsys), _ptr(x, m * nsys, f.dtype),
                                    _stream(stream))
@@ -385,7 +404,7 @@ def tf_plain_trsv_upper(m, U, f, x=None, stream=None):
 def tf_quadratic(a0, a1, b0, b1, c0, c1, out=None, stream=None):
     """Both roots (r0, r1, s0, s1) of a x^2 + b x + c = 0, twofold operands."""
     n = a0.numel()
-    out = tuple(_out(None, a0) for _ in range(4)) if out is None else out
+    out = tuple(_out(None, a0, stream) for _ in range(4)) if out is None else out
     st = lib().tf_quadratic(C.c_int(_dtype_code(a0)), C.c_int64(n),
                             *[_ptr(v, n, a0.dtype) for v in (a0, a1, b0, b1, c0, c1)],
                             *[_ptr(v, n, a0.dtype) for v in out], _stream(stream))
@@ -395,7 +414,7 @@ def tf_quadratic(a0, a1, b0, b1, c0, c1, out=None, stream=None):
 
 def tf_plain_quadratic(a, b, c, r=None, s=None, stream=None):
     n = a.numel()
-    r, s = _out(r, a), _out(s, a)
+    r, s = _out(r, a, stream), _out(s, a, stream)
     st = lib().tf_plain_quadratic(C.c_int(_dtype_code(a)), C.c_int64(n),
                                   *[_ptr(v, n, a.dtype) for v in (a, b, c, r, s)], _stream(stream))
     _check(st, "tf_plain_quadratic")
@@ -405,7 +424,7 @@ def tf_plain_quadratic(a, b, c, r=None, s=None, stream=None):
 def tf_fma(x0, x1, y0, y1, w0, w1, z0=None, z1=None, stream=None):
     """Twofold fused multiply-add z = x y + w; None low parts are dotted."""
     n = x0.numel()
-    z0, z1 = _out(z0, x0), _out(z1, x0)
+    z0, z1 = _out(z0, x0, stream), _out(z1, x0, stream)
     st = lib().tf_fma(C.c_int(_dtype_code(x0)), C.c_int64(n),
                       *[_ptr(v, n, x0.dtype) for v in (x0, x1, y0, y1, w0, w1, z0, z1)], _stream(stream))
     _check(st, "tf_fma")
@@ -414,7 +433,7 @@ def tf_fma(x0, x1, y0, y1, w0, w1, z0=None, z1=None, stream=None):
 
 def tf_plain_fma(x, y, w, z=None, stream=None):
     n = x.numel()
-    z = _out(z, x)
+    z = _out(z, x, stream)
     st = lib().tf_plain_fma(C.c_int(_dtype_code(x)), C.c_int64(n),
                             *[_ptr(v, n, x.dtype) for v in (x, y, w, z)], _stream(stream))
     _check(st, "tf_plain_fma")

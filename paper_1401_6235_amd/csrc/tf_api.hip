@@ -23,7 +23,10 @@ int num_cus() {
 
 static bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
 
+// Every entry point makes its Launch before its first kernel launch, which
+// starts the call's own launch status afresh.
 static Launch make_launch(hipStream_t stream, std::initializer_list<const void *> ptrs) {
+    call_status() = hipSuccess;
     Launch L;
     L.stream = stream;
     L.aligned = true;
@@ -35,10 +38,9 @@ static Launch make_launch(hipStream_t stream, std::initializer_list<const void *
 
 static int size_of(int dtype) { return dtype == TF_F64 ? 8 : dtype == TF_F32 ? 4 : 0; }
 
-static int finish() {
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TF_OK : TF_EDEVICE;
-}
+// The status of this call's launches only: an error that other code left
+// in the thread's HIP state is neither returned nor cleared.
+static int finish() { return call_status() == hipSuccess ? TF_OK : TF_EDEVICE; }
 
 }  // namespace tf
 

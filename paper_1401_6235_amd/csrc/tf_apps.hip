@@ -137,10 +137,10 @@ template <typename T, int M>
 static void launch_trsv_fixed(const Launch &L, int64_t nsys, const T *a0, const T *a1, const T *b0, const T *b1,
                               T *c0, T *c1) {
     const dim3 g(grid_for(nsys, kBlock, 0)), b(kBlock);
-    if (a1 && b1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, true, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
-    else if (a1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, true, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
-    else if (b1) hipLaunchKernelGGL((trsv_fixed_kernel<T, M, false, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
-    else hipLaunchKernelGGL((trsv_fixed_kernel<T, M, false, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    if (a1 && b1) tf_launch((trsv_fixed_kernel<T, M, true, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else if (a1) tf_launch((trsv_fixed_kernel<T, M, true, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else if (b1) tf_launch((trsv_fixed_kernel<T, M, false, true>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
+    else tf_launch((trsv_fixed_kernel<T, M, false, false>), g, b, 0, L.stream, nsys, a0, a1, b0, b1, c0, c1);
 }
 
 template <typename T, int M = 1>
@@ -152,8 +152,8 @@ static bool dispatch_trsv_fixed(const Launch &L, int m, int64_t nsys, const T *a
         if (m != M)
             return dispatch_trsv_fixed<T, M + 1>(L, m, nsys, a0, a1, b0, b1, c0, c1, pu, pf, px, plain);
         if (plain)
-            hipLaunchKernelGGL((plain_trsv_fixed_kernel<T, M>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0,
-                               L.stream, nsys, pu, pf, px);
+            tf_launch((plain_trsv_fixed_kernel<T, M>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0,
+                      L.stream, nsys, pu, pf, px);
         else
             launch_trsv_fixed<T, M>(L, nsys, a0, a1, b0, b1, c0, c1);
         return true;
@@ -180,17 +180,17 @@ void run_trsv(const Launch &L, int64_t nsys, int m, const void *U0, const void *
     T *c0 = (T *)x0, *c1 = (T *)x1;
     if (dispatch_trsv_fixed<T>(L, m, nsys, a0, a1, b0, b1, c0, c1, nullptr, nullptr, nullptr, false)) return;
     if (U1 && f1)
-        hipLaunchKernelGGL((trsv_kernel<T, true, true>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0, a1, b0,
-                           b1, c0, c1);
+        tf_launch((trsv_kernel<T, true, true>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0, a1, b0,
+                  b1, c0, c1);
     else if (U1)
-        hipLaunchKernelGGL((trsv_kernel<T, true, false>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0, a1,
-                           b0, nullptr, c0, c1);
+        tf_launch((trsv_kernel<T, true, false>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0, a1,
+                  b0, nullptr, c0, c1);
     else if (f1)
-        hipLaunchKernelGGL((trsv_kernel<T, false, true>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0,
-                           nullptr, b0, b1, c0, c1);
+        tf_launch((trsv_kernel<T, false, true>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0,
+                  nullptr, b0, b1, c0, c1);
     else
-        hipLaunchKernelGGL((trsv_kernel<T, false, false>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0,
-                           nullptr, b0, nullptr, c0, c1);
+        tf_launch((trsv_kernel<T, false, false>), dim3(g), dim3(kBlock), 0, L.stream, nsys, m, a0,
+                  nullptr, b0, nullptr, c0, c1);
 }
 template void run_trsv<double>(const Launch &, int64_t, int, const void *, const void *, const void *,
                                const void *, void *, void *);
@@ -202,8 +202,8 @@ void run_plain_trsv(const Launch &L, int64_t nsys, int m, const void *U, const v
     if (dispatch_trsv_fixed<T>(L, m, nsys, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (const T *)U,
                                (const T *)f, (T *)x, true))
         return;
-    hipLaunchKernelGGL((plain_trsv_kernel<T>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0, L.stream, nsys,
-                       m, (const T *)U, (const T *)f, (T *)x);
+    tf_launch((plain_trsv_kernel<T>), dim3(grid_for(nsys, kBlock, 0)), dim3(kBlock), 0, L.stream, nsys,
+              m, (const T *)U, (const T *)f, (T *)x);
 }
 template void run_plain_trsv<double>(const Launch &, int64_t, int, const void *, const void *, void *);
 template void run_plain_trsv<float>(const Launch &, int64_t, int, const void *, const void *, void *);
@@ -299,11 +299,11 @@ void run_quadratic(const Launch &L, int64_t n, const void *const *in, void *cons
     const T *c0 = (const T *)in[4], *c1 = (const T *)in[5];
     T *r0 = (T *)out[0], *r1 = (T *)out[1], *s0 = (T *)out[2], *s1 = (T *)out[3];
     if (L.aligned)
-        hipLaunchKernelGGL((quadratic_vec_kernel<T>), dim3(grid_for(n / Vec<T>::N, kBlock, L.cap)), dim3(kBlock), 0,
-                           L.stream, n, a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
+        tf_launch((quadratic_vec_kernel<T>), dim3(grid_for(n / Vec<T>::N, kBlock, L.cap)), dim3(kBlock), 0,
+                  L.stream, n, a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
     else
-        hipLaunchKernelGGL((quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
-                           a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
+        tf_launch((quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
+                  a0, a1, b0, b1, c0, c1, r0, r1, s0, s1);
 }
 template void run_quadratic<double>(const Launch &, int64_t, const void *const *, void *const *);
 template void run_quadratic<float>(const Launch &, int64_t, const void *const *, void *const *);
@@ -311,8 +311,8 @@ template void run_quadratic<float>(const Launch &, int64_t, const void *const *,
 template <typename T>
 void run_plain_quadratic(const Launch &L, int64_t n, const void *a, const void *b, const void *c, void *r,
                          void *s) {
-    hipLaunchKernelGGL((plain_quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream,
-                       n, (const T *)a, (const T *)b, (const T *)c, (T *)r, (T *)s);
+    tf_launch((plain_quadratic_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream,
+              n, (const T *)a, (const T *)b, (const T *)c, (T *)r, (T *)s);
 }
 template void run_plain_quadratic<double>(const Launch &, int64_t, const void *, const void *, const void *,
                                           void *, void *);
@@ -400,12 +400,12 @@ __global__ __launch_bounds__(kBlock) void fma_scalar_kernel(int64_t n, const T *
 template <typename T, bool XT, bool YT, bool WT>
 static void launch_fma(const Launch &L, int64_t n, const T *const *p, T *z0, T *z1) {
     if (L.aligned)
-        hipLaunchKernelGGL((fma_vec_kernel<T, XT, YT, WT>),
-                           dim3(grid_for((n / Vec<T>::N + FmaUnroll<T>::U - 1) / FmaUnroll<T>::U, kBlock, L.cap)),
-                           dim3(kBlock), 0, L.stream, n, p[0], p[1], p[2], p[3], p[4], p[5], z0, z1);
+        tf_launch((fma_vec_kernel<T, XT, YT, WT>),
+                  dim3(grid_for((n / Vec<T>::N + FmaUnroll<T>::U - 1) / FmaUnroll<T>::U, kBlock, L.cap)),
+                  dim3(kBlock), 0, L.stream, n, p[0], p[1], p[2], p[3], p[4], p[5], z0, z1);
     else
-        hipLaunchKernelGGL((fma_scalar_kernel<T, XT, YT, WT>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0,
-                           L.stream, n, p[0], p[1], p[2], p[3], p[4], p[5], z0, z1);
+        tf_launch((fma_scalar_kernel<T, XT, YT, WT>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0,
+                  L.stream, n, p[0], p[1], p[2], p[3], p[4], p[5], z0, z1);
 }
 
 template <typename T>
@@ -436,8 +436,8 @@ __global__ __launch_bounds__(kBlock) void plain_fma_kernel(int64_t n, const T *x
 
 template <typename T>
 void run_plain_fma(const Launch &L, int64_t n, const void *x, const void *y, const void *w, void *z) {
-    hipLaunchKernelGGL((plain_fma_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
-                       (const T *)x, (const T *)y, (const T *)w, (T *)z);
+    tf_launch((plain_fma_kernel<T>), dim3(grid_for(n, kBlock, L.cap)), dim3(kBlock), 0, L.stream, n,
+              (const T *)x, (const T *)y, (const T *)w, (T *)z);
 }
 template void run_plain_fma<double>(const Launch &, int64_t, const void *, const void *, const void *, void *);
 template void run_plain_fma<float>(const Launch &, int64_t, const void *, const void *, const void *, void *);

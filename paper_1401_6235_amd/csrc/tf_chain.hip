@@ -92,11 +92,11 @@ static void launch_chain(const Launch &L, int64_t n, int64_t reps, const T *x0, 
     constexpr int C = TF_CHAIN_C;
     const unsigned g = grid_for(n, (int64_t)kBlock * C, 0);
     if (y1 && !op_unary(OP))
-        hipLaunchKernelGGL((chain_kernel<T, OP, true, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, x0, x1,
-                           y0, y1, z0, z1);
+        tf_launch((chain_kernel<T, OP, true, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, x0, x1,
+                  y0, y1, z0, z1);
     else
-        hipLaunchKernelGGL((chain_kernel<T, OP, false, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, x0,
-                           x1, y0, nullptr, z0, z1);
+        tf_launch((chain_kernel<T, OP, false, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, x0,
+                  x1, y0, nullptr, z0, z1);
 }
 
 // Operation code of one chain step: mode 0 twofold, 1 coupled, 2 Dekker.
@@ -145,7 +145,7 @@ void run_plain_chain(const Launch &L, int op, int64_t n, int64_t reps, const voi
     switch (op) {
 #define TF_PCHAIN_CASE(K)                                                                          \
     case K:                                                                                        \
-        hipLaunchKernelGGL((plain_chain_kernel<T, K, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, a, b, c); \
+        tf_launch((plain_chain_kernel<T, K, C>), dim3(g), dim3(kBlock), 0, L.stream, n, reps, a, b, c); \
         break;
         TF_PCHAIN_CASE(OP_ADD)
         TF_PCHAIN_CASE(OP_SUB)

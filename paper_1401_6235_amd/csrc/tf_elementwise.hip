@@ -113,12 +113,12 @@ static void launch_ew(const Launch &L, int64_t n, const T *x0, const T *x1, cons
     if (L.aligned) {
         const int64_t nvec = n / Vec<T>::N;
         const unsigned g = grid_for(nvec, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
-        hipLaunchKernelGGL((ew_vec_kernel<T, OP, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream,
-                           n, x0, x1, y0, y1, z0, z1);
+        tf_launch((ew_vec_kernel<T, OP, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream,
+                  n, x0, x1, y0, y1, z0, z1);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);
-        hipLaunchKernelGGL((ew_scalar_kernel<T, OP, XT, YT>), dim3(g), dim3(kBlock), 0, L.stream, n,
-                           x0, x1, y0, y1, z0, z1);
+        tf_launch((ew_scalar_kernel<T, OP, XT, YT>), dim3(g), dim3(kBlock), 0, L.stream, n,
+                  x0, x1, y0, y1, z0, z1);
     }
 }
 
@@ -238,11 +238,11 @@ static void launch_plain(const Launch &L, int64_t n, const T *x, const T *y, T *
     constexpr int UNROLL = TF_PLAIN_UNROLL;
     if (L.aligned) {
         const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
-        hipLaunchKernelGGL((plain_vec_kernel<T, OP, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n, x,
-                           y, z);
+        tf_launch((plain_vec_kernel<T, OP, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n, x,
+                  y, z);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);
-        hipLaunchKernelGGL((plain_scalar_kernel<T, OP>), dim3(g), dim3(kBlock), 0, L.stream, n, x, y, z);
+        tf_launch((plain_scalar_kernel<T, OP>), dim3(g), dim3(kBlock), 0, L.stream, n, x, y, z);
     }
 }
 
@@ -335,12 +335,12 @@ static void launch_axpy(const Launch &L, int64_t n, T a0, T a1, const T *x0, con
     constexpr int UNROLL = sizeof(T) == 8 ? TF_EW_UNROLL_F64 : TF_EW_UNROLL_F32;
     if (L.aligned) {
         const unsigned g = grid_for(n / Vec<T>::N, (int64_t)kEwBlock * UNROLL * TF_EW_CHUNK, L.cap);
-        hipLaunchKernelGGL((axpy_vec_kernel<T, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n,
-                           a0, a1, x0, x1, y0, y1, z0, z1);
+        tf_launch((axpy_vec_kernel<T, XT, YT, UNROLL>), dim3(g), dim3(kEwBlock), 0, L.stream, n,
+                  a0, a1, x0, x1, y0, y1, z0, z1);
     } else {
         const unsigned g = grid_for(n, kBlock, L.cap);
-        hipLaunchKernelGGL((axpy_scalar_kernel<T, XT, YT>), dim3(g), dim3(kBlock), 0, L.stream, n, a0,
-                           a1, x0, x1, y0, y1, z0, z1);
+        tf_launch((axpy_scalar_kernel<T, XT, YT>), dim3(g), dim3(kBlock), 0, L.stream, n, a0,
+                  a1, x0, x1, y0, y1, z0, z1);
     }
 }
 
@@ -381,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void plain_axpy_kernel(int64_t n, T a, cons
 template <typename T>
 void run_plain_axpy(const Launch &L, int64_t n, const void *a, const void *x, const void *y, void *z) {
     const unsigned g = grid_for(L.aligned ? n / Vec<T>::N : n, kBlock, L.cap);
-    hipLaunchKernelGGL((plain_axpy_kernel<T>), dim3(g), dim3(kBlock), 0, L.stream, n, ((const T *)a)[0],
-                       (const T *)x, (const T *)y, (T *)z, (int)L.aligned);
+    tf_launch((plain_axpy_kernel<T>), dim3(g), dim3(kBlock), 0, L.stream, n, ((const T *)a)[0],
+              (const T *)x, (const T *)y, (T *)z, (int)L.aligned);
 }
 template void run_plain_axpy<double>(const Launch &, int64_t, const void *, const void *, const void *,
                                      void *);
@@ -428,11 +428,11 @@ void run_horner(const Launch &L, int64_t n, int degree, const void *c, const voi
     for (int k = 0; k <= degree; ++k) C.c[k] = ((const T *)c)[k];
     const unsigned g = grid_for(L.aligned ? n / Vec<T>::N : n, kBlock, L.cap);
     if (x1)
-        hipLaunchKernelGGL((horner_kernel<T, true>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
-                           (const T *)x0, (const T *)x1, (T *)z0, (T *)z1, (int)L.aligned);
+        tf_launch((horner_kernel<T, true>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
+                  (const T *)x0, (const T *)x1, (T *)z0, (T *)z1, (int)L.aligned);
     else
-        hipLaunchKernelGGL((horner_kernel<T, false>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
-                           (const T *)x0, (const T *)nullptr, (T *)z0, (T *)z1, (int)L.aligned);
+        tf_launch((horner_kernel<T, false>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
+                  (const T *)x0, (const T *)nullptr, (T *)z0, (T *)z1, (int)L.aligned);
 }
 template void run_horner<double>(const Launch &, int64_t, int, const void *, const void *, const void *,
                                  void *, void *);
@@ -469,8 +469,8 @@ void run_plain_horner(const Launch &L, int64_t n, int degree, const void *c, con
     Coeffs<T> C{};
     for (int k = 0; k <= degree; ++k) C.c[k] = ((const T *)c)[k];
     const unsigned g = grid_for(L.aligned ? n / Vec<T>::N : n, kBlock, L.cap);
-    hipLaunchKernelGGL((plain_horner_kernel<T>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
-                       (const T *)x, (T *)z, (int)L.aligned);
+    tf_launch((plain_horner_kernel<T>), dim3(g), dim3(kBlock), 0, L.stream, n, degree, C,
+              (const T *)x, (T *)z, (int)L.aligned);
 }
 template void run_plain_horner<double>(const Launch &, int64_t, int, const void *, const void *, void *);
 template void run_plain_horner<float>(const Launch &, int64_t, int, const void *, const void *, void *);

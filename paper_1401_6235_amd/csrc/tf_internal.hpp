@@ -6,6 +6,7 @@
 
 #include "tf.h"
 #include "tf_kernels.hpp"
+#include "tf_launch.hpp"
 
 namespace tf {
 

@@ -87,15 +87,15 @@ static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, 
                           const T *y1, T *out, Pair<T> *work) {
     constexpr bool PLAIN = LeafTraits<LEAF>::plain;
     if (n == 0) {  // empty: the partial pass over zero partials writes (+0, +0)
-        hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3(1), dim3(kBlock), 0, L.stream,
-                           (int64_t)0, (int64_t)1, (const Pair<T> *)nullptr, (Pair<T> *)nullptr, out);
+        tf_launch((reduce_partials_kernel<T, PLAIN>), dim3(1), dim3(kBlock), 0, L.stream,
+                  (int64_t)0, (int64_t)1, (const Pair<T> *)nullptr, (Pair<T> *)nullptr, out);
         return;
     }
     const RedShape s = reduce_shape(n);
     const bool single = s.padded == 1;
-    hipLaunchKernelGGL((reduce_tiles_kernel<T, LEAF>), dim3((unsigned)s.blocks), dim3(kBlock), 0, L.stream,
-                       n, s.tiles, (int)s.per_block, (int)L.aligned, x0, x1, y0, y1, work,
-                       single ? out : (T *)nullptr);
+    tf_launch((reduce_tiles_kernel<T, LEAF>), dim3((unsigned)s.blocks), dim3(kBlock), 0, L.stream,
+              n, s.tiles, (int)s.per_block, (int)L.aligned, x0, x1, y0, y1, work,
+              single ? out : (T *)nullptr);
     int64_t count = s.blocks, padded = s.padded;
     Pair<T> *src = work;
     while (padded > 1) {
@@ -105,11 +105,11 @@ static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, 
         Pair<T> *dst = src + count;
         const bool last = next_padded == 1;
         if (last && span >= kWideBlock / 64)
-            hipLaunchKernelGGL((reduce_last_kernel<T, PLAIN>), dim3(1), dim3(kWideBlock), 0, L.stream, count, span,
-                               (const Pair<T> *)src, out);
+            tf_launch((reduce_last_kernel<T, PLAIN>), dim3(1), dim3(kWideBlock), 0, L.stream, count, span,
+                      (const Pair<T> *)src, out);
         else
-            hipLaunchKernelGGL((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
-                               L.stream, count, span, (const Pair<T> *)src, dst, last ? out : (T *)nullptr);
+            tf_launch((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
+                      L.stream, count, span, (const Pair<T> *)src, dst, last ? out : (T *)nullptr);
         src = dst;
         count = next_count;
         padded = next_padded;

@@ -654,8 +654,9 @@ class HipDevice : public tfs::DeviceOps {
         // shared with other streams of the process, whose work waits until
         // it exits; the host relaunches it with the next job.
         const uint64_t idle = (uint64_t)(0.02 * tick_hz_);
-        hipLaunchKernelGGL(serve_kernel, dim3(1 + workers_), dim3(kBlock), 0, work_, shared_, state_, idle);
-        return hipGetLastError() == hipSuccess ? TF_OK : TF_EDEVICE;
+        return tf_launch(serve_kernel, dim3(1 + workers_), dim3(kBlock), 0, work_, shared_, state_, idle) == hipSuccess
+                   ? TF_OK
+                   : TF_EDEVICE;
     }
     bool running() override { return hipStreamQuery(work_) == hipErrorNotReady; }
     int stop() override {

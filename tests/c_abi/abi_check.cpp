@@ -143,6 +143,27 @@ int main() {
         (void)hipFree(work);
         (void)hipFree(out);
     }
+    // An error that other code left in the thread's HIP state is neither
+    // returned by a tf_* call as its own nor cleared by it.
+    {
+        const int64_t m = 1000;
+        std::vector<double> a = draw<double>(m, 31, 1.0), b = draw<double>(m, 32, 1.0);
+        double *da = dev(a), *db = dev(b), *o0 = dev(a), *o1 = dev(a);
+        (void)hipGetLastError();
+        int ndev = 0;
+        const hipError_t planted = hipSetDevice(-1);  // invalid ordinal: fails, sets nothing
+        (void)hipGetDeviceCount(&ndev);                // a successful call in between
+        const bool sticky = planted != hipSuccess && hipPeekAtLastError() == planted;
+        const int st = tf_add(TF_F64, m, da, nullptr, db, nullptr, o0, o1, nullptr);
+        report("foreign pending error not returned", st == TF_OK);
+        if (sticky) report("foreign pending error not cleared", hipPeekAtLastError() == planted);
+        else std::printf("%-34s %s\n", "foreign pending error not cleared", "skipped (runtime keeps no sticky error)");
+        (void)hipGetLastError();
+        std::vector<double> z0(m), z1(m);
+        orc_add_f64(m, a.data(), nullptr, b.data(), nullptr, z0.data(), z1.data());
+        report("tf_add after a foreign error", same_bits(host(o0, m), z0) && same_bits(host(o1, m), z1));
+        for (double *p : {da, db, o0, o1}) (void)hipFree(p);
+    }
     // misuse is reported, not run
     report("invalid dtype", tf_add(7, 10, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == TF_EINVAL);
     report("NULL output", tf_sqrt(TF_F64, 10, (void *)16, nullptr, nullptr, nullptr, nullptr) == TF_EINVAL);

@@ -186,32 +186,68 @@ def test_plain_kernels(dtype):
     assert_bits(to_np(z[0]), oracle.plain_axpy(a["a"][0], a["x0"], a["y0"]), "axpy z0 = plain")
 
 
-def test_full_size_sampled():
-    """The n = 2^28 binary64 axpy and Horner workloads in the benchmark's
-    launch configuration; 200k sampled outputs checked one by one."""
+def _f32_bounds(kind, case, idx, z0, z1, count):
+    """binary32 z1 on `count` of the sampled elements against the binary64
+    reference deviation of z0, within the running bound of the element's
+    steps at u = 2^-24 plus the reference's own error (the same bound
+    scaled to u = 2^-53, with a factor 2 to spare, and 2^-52 |dz0|)."""
+    from exact import F
+    from test_oracle_bounds import axpy_bound, horner_bound
+    j = idx[:count]
+    f32 = np.float32
+    if kind == "axpy":
+        dz = oracle.ref64("axpy", case["a"], case["x0"][j], case["x1"][j], case["y0"][j], case["y1"][j], z0[:count])
+    else:
+        dz = oracle.ref64("horner", case["c"], case["x0"][j], case["x1"][j], z0[:count])
+    for k, i in enumerate(j):
+        if kind == "axpy":
+            b, exact = axpy_bound(case["a"], case["x0"][i], case["x1"][i], case["y0"][i], case["y1"][i], z0[k], f32)
+        else:
+            b, exact = horner_bound(case["c"], case["x0"][i], case["x1"][i], z0[k], f32)
+        slack = b / 2 ** 28 + abs(exact) / 2 ** 52
+        assert abs(F(dz[k]) - exact) <= slack, (kind, i)
+        assert abs(F(z1[k]) - F(dz[k])) <= b + 2 * slack, (kind, i)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_full_size_sampled(dtype):
+    """The n = 2^28 axpy and Horner workloads in the benchmark's launch
+    configuration; 200k sampled outputs checked one by one against the
+    oracle.  binary32 z1 is also judged against the binary64 reference
+    deviation on 2000 of them, within each element's running bound."""
     torch = torch_cuda()
     n = 1 << 28
+    name = np.dtype(dtype).name
     g = np.random.default_rng(77)
     idx = np.unique(np.concatenate([g.integers(0, n, 200000), [0, 1, n - 2, n - 1]]))
-    step("full-size axpy n=2^28 (generate)")
-    c = W.axpy_case(n, seed=0, dtype=np.float64)
+    g.shuffle(idx)
+    step("full-size axpy %s n=2^28 (generate)" % name)
+    c = W.axpy_case(n, seed=0, dtype=dtype)
     gpu = {k: to_gpu(v) for k, v in c.items() if k != "a"}
-    step("full-size axpy n=2^28 (run)")
+    step("full-size axpy %s n=2^28 (run)" % name)
     z = tf.tf_axpy(c["a"], gpu["x0"], gpu["x1"], gpu["y0"], gpu["y1"])
     torch.cuda.synchronize()
     want = oracle.axpy(c["a"], c["x0"][idx], c["x1"][idx], c["y0"][idx], c["y1"][idx])
     ii = torch.from_numpy(idx).cuda()
-    assert_bits(to_np(z[0][ii]), want[0], "axpy z0")
-    assert_bits(to_np(z[1][ii]), want[1], "axpy z1")
+    got = (to_np(z[0][ii]), to_np(z[1][ii]))
+    assert_bits(got[0], want[0], "axpy z0")
+    assert_bits(got[1], want[1], "axpy z1")
+    if dtype == np.float32:
+        _f32_bounds("axpy", c, idx, got[0], got[1], 2000)
     del gpu, z, c
     torch.cuda.empty_cache()
-    step("full-size horner n=2^28")
-    h = W.horner_case(n, seed=0, dtype=np.float64)
+    step("full-size horner %s n=2^28" % name)
+    h = W.horner_case(n, seed=0, dtype=dtype)
     z = tf.tf_horner(h["c"], to_gpu(h["x0"]), to_gpu(h["x1"]))
     torch.cuda.synchronize()
     want = oracle.horner(h["c"], h["x0"][idx], h["x1"][idx])
-    assert_bits(to_np(z[0][ii]), want[0], "horner z0")
-    assert_bits(to_np(z[1][ii]), want[1], "horner z1")
+    got = (to_np(z[0][ii]), to_np(z[1][ii]))
+    assert_bits(got[0], want[0], "horner z0")
+    assert_bits(got[1], want[1], "horner z1")
+    if dtype == np.float32:
+        _f32_bounds("horner", h, idx, got[0], got[1], 2000)
+    del z, h
+    torch.cuda.empty_cache()
 
 
 def test_repeat_and_grid_cap_are_bitwise_stable():

@@ -115,19 +115,62 @@ def test_full_size_ill_conditioned_f64(cond):
     assert_bits(to_np(tf.tf_plain_dot(gx, gy)), np.array([oracle.plain_dot(d["x"], d["y"])]), "plain dot")
 
 
+def tree_depth(n):
+    """Levels of the reduction tree: 8 inside a 256-leaf tile, then one per
+    doubling of the padded tile count."""
+    tiles = max(1, -(-n // 256))
+    return 8 + (tiles - 1).bit_length()
+
+
+def tree_bound(n, u, A, lam=None):
+    """|z0 + z1 - exact| for the twofold tree over leaves (L0, L1) with
+    |L1| <= lam |L0 + L1|: a node's rounding error e is exact and z1 gathers
+    the leaves' low parts and the node errors with two roundings per node.
+    With lam <= u (Two-Product leaves, an exact product split in the same
+    format) that is (d^2 + 4d) u^2 sum|leaf| to first order; a larger lam
+    adds 2 d u lam sum|leaf| (the low parts rounded once per level).  A
+    factor 2 covers the higher-order terms."""
+    d = tree_depth(n)
+    b = (d * d + 4 * d) * u * u * A
+    if lam is not None and lam > u:
+        b += 2 * d * u * lam * A
+    return 2 * b
+
+
 @pytest.mark.parametrize("cond", [1e4, 1e8, 1e16])
 def test_full_size_ill_conditioned_f32(cond):
+    """n = 2^26 binary32, bit for bit against the oracle; then z0 + z1
+    against the exact dot (the generator's fixed-point accumulator, rounded
+    once to binary64) within the tree bound at u = 2^-24, and z1 against the
+    binary64 reference deviation of z0 within the same bound plus the
+    reference's own error: the tree bound at u = 2^-53 (the widened dot's
+    products are exact; the widened sum's leaves keep low parts up to
+    2^-24 of their value), doubled, and two binary64 roundings of the
+    deviation."""
+    from fractions import Fraction as Fr
     n = 1 << 26
+    u32, u64 = 2.0 ** -24, 2.0 ** -53
     step("illdot f32 n=2^26 cond=%g" % cond)
     d = W.illdot_case(n, cond, seed=0, dtype=np.float32)
     hi, lo = W.product_split(d["x"], d["y"])
     gx, gy, ghi, glo = (to_gpu(v) for v in (d["x"], d["y"], hi, lo))
-    got = to_np(tf.tf_dot(gx, None, gy, None))
-    assert_bits(got, np.array(oracle.dot(d["x"], None, d["y"], None)), "dot")
-    assert_bits(to_np(tf.tf_sum(ghi, glo)), np.array(oracle.sum(hi, lo)), "sum")
-    # binary32 z1 against the binary64 reference deviation of z0
-    dz = oracle.ref64("dot", d["x"], None, d["y"], None, got[0])
-    assert np.isfinite(dz[0])
+    dot = to_np(tf.tf_dot(gx, None, gy, None))
+    assert_bits(dot, np.array(oracle.dot(d["x"], None, d["y"], None)), "dot")
+    s = to_np(tf.tf_sum(ghi, glo))
+    assert_bits(s, np.array(oracle.sum(hi, lo)), "sum")
+    del gx, gy, ghi, glo
+    x64, y64 = d["x"].astype(np.float64), d["y"].astype(np.float64)
+    exact = W.exact_dot_f64(x64, y64)  # x^T y rounded once
+    A = float(np.abs(x64 * y64).sum()) * (1 + 2.0 ** -20)  # products exact; sum to 2^-27
+    b32 = tree_bound(n, u32, A)
+    for name, z, dz, lam in (("dot", dot, oracle.ref64("dot", d["x"], None, d["y"], None, dot[0]), 0.0),
+                             ("sum", s, oracle.ref64("sum", hi, lo, s[0]), u32)):
+        got = Fr(float(z[0])) + Fr(float(z[1]))
+        assert abs(got - Fr(exact)) <= Fr(b32) + Fr(u64 * abs(exact)), (name, cond)
+        ref_err = 2 * tree_bound(n, u64, A, lam) + 4 * u64 * abs(float(dz[0]))
+        assert abs(Fr(float(z[1])) - Fr(float(dz[0]))) <= Fr(b32) + Fr(ref_err), (name, cond)
+        # the reference itself is within its error of the exact deviation
+        assert abs(Fr(float(dz[0])) - (Fr(exact) - Fr(float(z[0])))) <= Fr(ref_err) + Fr(u64 * abs(exact))
 
 
 def test_repeat_is_bitwise_stable():
@@ -137,6 +180,36 @@ def test_repeat_is_bitwise_stable():
     b = gpu_all(*case)
     for k in a:
         assert_bits(a[k], b[k], k)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_side_stream_with_binding_workspace(dtype):
+    """tf_sum / tf_dot on a side stream (stream=) with the workspace and
+    output made by the binding.  The side stream is held back by copies
+    queued first; right after the calls return, the current stream
+    allocates buffers of the workspace's size and fills them.  A workspace
+    handed to those allocations would be overwritten before the reduction
+    reads its partials."""
+    torch = torch_cuda()
+    n = 3000017
+    case = random_case(n, dtype, 123)
+    g = [to_gpu(v) for v in case]
+    big = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+    big_out = torch.empty_like(big)
+    cur = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(cur)
+    step("side-stream reductions %s" % np.dtype(dtype))
+    for _ in range(8):
+        tf.tf_vmem(big, big, big_out, stream=side)
+    s = tf.tf_sum(g[0], g[1], stream=side)
+    d = tf.tf_dot(g[0], None, g[2], None, stream=side)
+    ws = tf.tf_reduce_workspace_bytes(tf.TF_F64 if dtype == np.float64 else tf.TF_F32, n)
+    junk = [torch.full((ws,), 255, dtype=torch.uint8, device="cuda") for _ in range(8)]
+    torch.cuda.synchronize()
+    assert_bits(to_np(s), np.array(oracle.sum(case[0], case[1])), "sum on a side stream")
+    assert_bits(to_np(d), np.array(oracle.dot(case[0], None, case[2], None)), "dot on a side stream")
+    del junk, big, big_out
 
 
 def test_workspace_too_small_is_an_error():
