@@ -154,6 +154,27 @@ int tf_sum(int dtype, int64_t n, const void *x0, const void *x1, void *out, void
 int tf_dot(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
            const void *y1, void *out, void *work, size_t work_bytes, hipStream_t stream);
 
+/* tf_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, tree and bits as tf_dot, with the partials kept in a
+ * statically allocated device array of TF_NOALLOC_SCRATCH_BYTES instead of
+ * a caller workspace.  Allocates nothing and calls no allocating routine;
+ * the caller still owns x0, x1, y0, y1 and out (arguments as tf_dot).
+ * Each GPU holds its own copy of the array, resident until the process
+ * ends; its address is looked up on the first call on that device (the
+ * device current at the call, which must be the stream's).  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other host threads) race and give undefined results; calls in
+ * one stream are ordered and safe.  Nothing in the array needs to start at
+ * zero: every partial is written before it is read.  TF_ENOMEM when the
+ * partials of n leaves at the current tiling do not fit (at the default
+ * 64 tiles per block: n <= 2^31 fits in both types, about 2^32 binary64 and
+ * 2^33 binary32 at most); TF_EINVAL as tf_dot; TF_EDEVICE when the address
+ * lookup or a launch fails. */
+#define TF_NOALLOC_SCRATCH_BYTES (4u << 20)
+int tf_dot_noalloc(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
+                   const void *y1, void *out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Plain (non-twofold) counterparts: the same kernels' standard results only
  * (z = the z0 the twofold call would produce, bit for bit), for measuring

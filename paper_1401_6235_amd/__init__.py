@@ -26,6 +26,7 @@ TF_MAX_DEGREE = 32
 TF_CFG_EW_BLOCKS_PER_CU = 1
 TF_CFG_RED_TILES_PER_BLOCK = 2
 TF_MAX_TRSV = 64
+TF_NOALLOC_SCRATCH_BYTES = 4 << 20
 TF_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4}
 TF_MODES = {"twofold": 0, "coupled": 1, "dekker": 2}
 
@@ -230,6 +231,18 @@ def tf_dot(x0, x1, y0, y1, out=None, work=None, stream=None):
                       _ptr(y0, n, x0.dtype), _ptr(y1, n, x0.dtype), _ptr(out, 2, x0.dtype), _ptr(work),
                       C.c_size_t(work.numel() * work.element_size()), _stream(stream))
     _check(st, "tf_dot")
+    return out
+
+
+def tf_dot_noalloc(x0, x1, y0, y1, out, stream=None):
+    """tf_dot with the partials in the library's static device array: no
+    workspace, no allocation (``out``, 2 elements of x0's dtype on the
+    device, is required).  Calls that overlap on one GPU race."""
+    n = x0.numel()
+    st = lib().tf_dot_noalloc(C.c_int(_dtype_code(x0)), C.c_int64(n), _ptr(x0, n), _ptr(x1, n, x0.dtype),
+                              _ptr(y0, n, x0.dtype), _ptr(y1, n, x0.dtype), _ptr(out, 2, x0.dtype),
+                              _stream(stream))
+    _check(st, "tf_dot_noalloc")
     return out
 
 

@@ -85,6 +85,9 @@ struct RedShape {
     int64_t padded;
 };
 RedShape reduce_shape(int64_t n);
+// Number of (z0, z1) partials a reduction of n leaves writes to its
+// workspace at the current tiling (0 when it needs none).
+int64_t reduce_work_pairs(int64_t n);
 
 template <typename T>
 void run_reduce(const Launch &L, int leaf, int64_t n, const void *x0, const void *x1, const void *y0,

@@ -82,6 +82,24 @@ RedShape reduce_shape(int64_t n) {
     return s;
 }
 
+// Partials launch_reduce stores in the workspace for n leaves: the first
+// pass's per-block partials and every further level that is not the last.
+int64_t reduce_work_pairs(int64_t n) {
+    if (n <= 0) return 0;
+    const RedShape s = reduce_shape(n);
+    int64_t total = 0, count = s.blocks, padded = s.padded;
+    if (padded > 1) total += count;
+    while (padded > 1) {
+        const int64_t span = padded < kMaxSpan ? padded : kMaxSpan;
+        const int64_t next_padded = padded / span;
+        const int64_t next_count = (count + span - 1) / span;
+        if (next_padded > 1) total += next_count;
+        count = next_count;
+        padded = next_padded;
+    }
+    return total;
+}
+
 template <typename T, int LEAF>
 static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, const T *y0,
                           const T *y1, T *out, Pair<T> *work) {

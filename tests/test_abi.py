@@ -62,6 +62,16 @@ def test_host_only_calls():
                              None) == -1
     assert lib.tf_quadratic(tf.TF_F64, i64(3), *([None] * 10), None) == -1
     assert lib.tf_fma(tf.TF_F32, i64(0), *([None] * 8), None) == 0
+    # the allocation-free dot validates its arguments and rejects, on the
+    # host and before any device call, partials beyond its static array
+    # (2^40 leaves need 2^26 partials at the default tiling)
+    dummy = ctypes.c_void_p(256)
+    assert lib.tf_dot_noalloc(7, i64(10), dummy, None, dummy, None, dummy, None) == -1
+    assert lib.tf_dot_noalloc(tf.TF_F64, i64(-1), dummy, None, dummy, None, dummy, None) == -1
+    assert lib.tf_dot_noalloc(tf.TF_F64, i64(10), None, None, dummy, None, dummy, None) == -1
+    assert lib.tf_dot_noalloc(tf.TF_F64, i64(10), dummy, None, dummy, None, None, None) == -1
+    assert lib.tf_dot_noalloc(tf.TF_F64, i64(1 << 40), dummy, None, dummy, None, dummy, None) == -3
+    assert lib.tf_dot_noalloc(tf.TF_F32, i64(1 << 40), dummy, None, dummy, None, dummy, None) == -3
 
 
 def test_c_consumer_builds():
