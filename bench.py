@@ -9,7 +9,9 @@ synthetic inputs, binary64 and binary32:
     sum (twofold leaves), dot (plain vectors)            n = 2^26, cond 1e16
 The same pass with the plain (non-twofold) kernels and the memory probe is
 timed right after, for the twofold/plain slowdown.  Then, outside the step:
-the in-register chains (every operation, twofold / coupled / Dekker, against
+the dotted and mixed operand forms at n = 2^28 (one operand dotted, both
+dotted: the exact transforms, the dotted square root) against the same plain
+kernels; the in-register chains (every operation, twofold / coupled / Dekker, against
 the plain chain: the paper's in-cache criterion), the batched applications
 and the fma, each against its plain kernel, and the paper's own slowdowns
 as context; then the serving stream (20,000 verification jobs at 2,000
@@ -495,7 +497,7 @@ def bench_key(name: str):
         return "axpy_" + t
     if re.search(r"\bhorner_kernel<\w+, true>", name):
         return "horner_" + t
-    m = re.search(r"reduce_tiles_kernel<\w+, (\d)>", name)
+    m = re.search(r"reduce_tiles_kernel<\w+, (\d),", name)
     if m and m.group(1) in ("1", "2"):
         return ("sum_" if m.group(1) == "1" else "dot_") + t
     if re.search(r"plain_vec_kernel<\w+, 99,", name):
@@ -769,6 +771,62 @@ PAPER_SLOWDOWN_SMALL = {"add": 6.48, "sub": 6.59, "mul": 3.95, "div": 2.23, "sqr
 PAPER_SLOWDOWN_MEDIUM = {"add": 2.04, "sub": 2.10, "mul": 2.00, "div": 2.23, "sqrt": 3.37}
 
 
+# The paper's Tables 1-2, large arrays, binary64 (Mflop/s): plain operations
+# and the twofold ones with one dotted operand (*1) or two (exact
+# transforms; for sqrt, the dotted argument, RPF1.1).  vsub is not listed:
+# vadd stands in for it.
+PAPER_PLAIN_LARGE_F64 = {"add": 484.135, "sub": 484.135, "mul": 485.604, "div": 356.078, "sqrt": 361.607}
+PAPER_ONE_DOTTED_LARGE_F64 = {"add": 259.465, "sub": 263.608, "mul": 279.025, "div": 160.605}
+PAPER_BOTH_DOTTED_LARGE_F64 = {"add": 306.501, "sub": 329.568, "mul": 331.331, "div": 158.014, "sqrt": 160.645}
+
+
+def dotted_forms_run(torch, tf, inputs, pper, steps, warmup):
+    """The dotted and mixed operand forms at n = 2^28: one operand dotted
+    (ATF1.1, STF1.1, MTF1.1, DTF1.1 with y dotted; the x-dotted forms), both
+    dotted (the exact transforms Two-Sum, Two-Diff, Two-Product and DTF1.1.1)
+    and the dotted square root (RPF1.1), each against the plain kernel of the
+    same operation timed in the plain pass."""
+    calls, words = [], {}
+    for key, d in inputs.items():
+        tag = "f64" if key == "float64" else "f32"
+        z0, z1 = d["z0"], d["z1"]
+        for op in ("add", "sub", "mul", "div"):
+            f = getattr(tf, "tf_" + op)
+            forms = (("y_dotted", lambda f=f, d=d, z0=z0, z1=z1: f(d["x0"], d["x1"], d["y0"], None, z0, z1), 5),
+                     ("x_dotted", lambda f=f, d=d, z0=z0, z1=z1: f(d["x0"], None, d["y0"], d["y1"], z0, z1), 5),
+                     ("both_dotted", lambda f=f, d=d, z0=z0, z1=z1: f(d["x0"], None, d["y0"], None, z0, z1), 4))
+            for form, fn, w in forms:
+                name = "%s_%s_%s" % (op, form, tag)
+                calls.append((name, N_STREAM, fn))
+                words[name] = w
+        name = "sqrt_dotted_%s" % tag
+        calls.append((name, N_STREAM, lambda d=d, z0=z0, z1=z1: tf.tf_sqrt(d["s0"], None, z0, z1)))
+        words[name] = 3
+    _, per = run_pass(torch, calls, steps, warmup)
+    out = {}
+    for name, n, _ in calls:
+        op, tag = name.split("_", 1)[0], name.rsplit("_", 1)[1]
+        es = 8 if tag == "f64" else 4
+        ms = per[name]["ms_avg"]
+        p = pper["plain_%s_%s" % (op, tag)]["ms_avg"]
+        v = pper["vmem_" + tag]["ms_avg"]
+        gbs = n * words[name] * es / ms / 1e6
+        out[name] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2), "gb_s": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "copy_frac": round(gbs / (n * 3 * es / v / 1e6), 4),
+                     "plain_ms": round(p, 4), "slowdown": round(ms / p, 3)}
+    ctx = {"source": "the paper's Tables 1-2, large arrays, binary64 (Intel Core i5-4200U, AVX2)",
+           "paper_one_dotted": {op: round(PAPER_PLAIN_LARGE_F64[op] / v, 3)
+                                for op, v in PAPER_ONE_DOTTED_LARGE_F64.items()},
+           "paper_both_dotted": {op: round(PAPER_PLAIN_LARGE_F64[op] / v, 3)
+                                 for op, v in PAPER_BOTH_DOTTED_LARGE_F64.items()},
+           "ours_y_dotted_f64": {op: out["%s_y_dotted_f64" % op]["slowdown"] for op in ("add", "sub", "mul", "div")},
+           "ours_both_dotted_f64": dict({op: out["%s_both_dotted_f64" % op]["slowdown"]
+                                         for op in ("add", "sub", "mul", "div")},
+                                        sqrt=out["sqrt_dotted_f64"]["slowdown"])}
+    return {"n": N_STREAM, "forms": out, "paper_context": ctx}
+
+
 def paper_context(kernels, in_register, cache_resident=None):
     """The paper's slowdowns beside ours (binary64): HBM-resident arrays
     against its large arrays, cache-resident ones against its medium (L3)
@@ -906,6 +964,9 @@ def main():
         "kernels": kernels,
         "kernel_source_hash": src_hash,
     }
+    if not args.no_extra:
+        log("dotted and mixed operand forms (n = 2^28)")
+        result["dotted_forms"] = dotted_forms_run(torch, tf, inputs, pper, args.steps, args.warmup)
     # the timed passes' buffers are no longer needed
     del inputs, tcalls, pcalls
     torch.cuda.empty_cache()

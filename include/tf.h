@@ -166,11 +166,12 @@ int tf_dot(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
  * GPU shares that GPU's array, so calls that overlap on one GPU (other
  * streams, other host threads) race and give undefined results; calls in
  * one stream are ordered and safe.  Nothing in the array needs to start at
- * zero: every partial is written before it is read.  TF_ENOMEM when the
- * partials of n leaves at the current tiling do not fit (at the default
- * 64 tiles per block: n <= 2^31 fits in both types, about 2^32 binary64 and
- * 2^33 binary32 at most); TF_EINVAL as tf_dot; TF_EDEVICE when the address
- * lookup or a launch fails. */
+ * zero: every partial is written before it is read.  When the partials of
+ * n leaves at the current tiling would not fit, the call takes more tiles
+ * per block (the tree, and so the result, does not depend on it); TF_ENOMEM
+ * when even 256 tiles per block leave too many (n beyond about 2^34 in
+ * binary64, 2^35 in binary32); TF_EINVAL as tf_dot; TF_EDEVICE when the
+ * address lookup or a launch fails. */
 #define TF_NOALLOC_SCRATCH_BYTES (4u << 20)
 int tf_dot_noalloc(int dtype, int64_t n, const void *x0, const void *x1, const void *y0,
                    const void *y1, void *out, hipStream_t stream);
@@ -310,12 +311,17 @@ int tf_plain_fma(int dtype, int64_t n, const void *x, const void *y, const void 
  *   TF_CFG_EW_BLOCKS_PER_CU    cap on the elementwise grid, in blocks per
  *                              compute unit (0 = one block per 256 threads'
  *                              worth of work, no cap; default 0)
- *   TF_CFG_RED_TILES_PER_BLOCK 256-leaf tiles per reduction block, a power
- *                              of two in [1, 64] (default 64)
+ *   TF_CFG_RED_TILES_PER_BLOCK 256-leaf tiles per first-pass reduction
+ *                              block, a power of two in [1, 256], or 0
+ *                              (default) for the tuned value of each type
+ *                              and leaf kind
+ *   TF_CFG_RED_WAVES           waves per first-pass reduction block: 4, 8,
+ *                              16, or 0 (default) for the tuned value
  * Returns the previous value, or TF_EINVAL for an unknown key or value.
  * ---------------------------------------------------------------------- */
 #define TF_CFG_EW_BLOCKS_PER_CU 1
 #define TF_CFG_RED_TILES_PER_BLOCK 2
+#define TF_CFG_RED_WAVES 3
 int64_t tf_config(int key, int64_t value);
 
 /* ------------------------------------------------------------------------

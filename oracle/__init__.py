@@ -22,7 +22,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtforacle.so")
+# TF_ORACLE_LIB selects another build of the library (the sanitizer tests use it)
+LIB_PATH = os.environ.get("TF_ORACLE_LIB") or os.path.join(_HERE, "libtforacle.so")
 SOURCES = [os.path.join(_HERE, "tf_oracle.c"), os.path.join(_HERE, "tf_oracle_t.h")]
 
 # Contraction off and no fast-math: every a*b+c stays a multiply and an add.

@@ -25,6 +25,7 @@ TF_OK = 0
 TF_MAX_DEGREE = 32
 TF_CFG_EW_BLOCKS_PER_CU = 1
 TF_CFG_RED_TILES_PER_BLOCK = 2
+TF_CFG_RED_WAVES = 3
 TF_MAX_TRSV = 64
 TF_NOALLOC_SCRATCH_BYTES = 4 << 20
 TF_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4}

@@ -76,9 +76,15 @@ int64_t tf_config(int key, int64_t value) {
         return old;
     }
     if (key == TF_CFG_RED_TILES_PER_BLOCK) {
-        if (value < 1 || value > 64 || (value & (value - 1))) return TF_EINVAL;
+        if (value < 0 || value > 256 || (value & (value - 1))) return TF_EINVAL;
         const int64_t old = c.red_tiles_per_block;
         c.red_tiles_per_block = value;
+        return old;
+    }
+    if (key == TF_CFG_RED_WAVES) {
+        if (value != 0 && value != 4 && value != 8 && value != 16) return TF_EINVAL;
+        const int64_t old = c.red_waves;
+        c.red_waves = value;
         return old;
     }
     return TF_EINVAL;
@@ -160,8 +166,9 @@ static int reduce(int leaf, int dtype, int64_t n, const void *x0, const void *x1
     if (n > 0) TF_CHECK(x0);
     if (need > 0 && (work == nullptr || work_bytes < need)) return TF_ENOMEM;
     const Launch L = make_launch(stream, {x0, x1, y0, y1});
-    if (dtype == TF_F64) run_reduce<double>(L, leaf, n, x0, x1, y0, y1, out, work);
-    else run_reduce<float>(L, leaf, n, x0, x1, y0, y1, out, work);
+    const int64_t pb = tiles_per_block(size_of(dtype), leaf);
+    if (dtype == TF_F64) run_reduce<double>(L, leaf, n, pb, x0, x1, y0, y1, out, work);
+    else run_reduce<float>(L, leaf, n, pb, x0, x1, y0, y1, out, work);
     return finish();
 }
 

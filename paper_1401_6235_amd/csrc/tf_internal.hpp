@@ -20,7 +20,8 @@ struct Launch {
 // Process-wide launch settings (tf_config).
 struct Config {
     int64_t ew_blocks_per_cu = 0;
-    int64_t red_tiles_per_block = 64;
+    int64_t red_tiles_per_block = 0;  // 0: tuned per element size and leaf kind
+    int64_t red_waves = 0;            // waves per first-pass block; 0: tuned
 };
 Config &config();
 int num_cus();
@@ -84,13 +85,18 @@ struct RedShape {
     int64_t blocks;
     int64_t padded;
 };
-RedShape reduce_shape(int64_t n);
-// Number of (z0, z1) partials a reduction of n leaves writes to its
-// workspace at the current tiling (0 when it needs none).
-int64_t reduce_work_pairs(int64_t n);
+RedShape reduce_shape(int64_t n, int64_t per_block);
+// Tiles per first-pass block for this element size and leaf kind: the
+// configured value, or the tuned default when none is configured.
+int64_t tiles_per_block(int elem_size, int leaf);
+// Largest tiles-per-block value a first-pass block handles (64 per wave).
+constexpr int64_t kMaxTilesPerBlock = 256;
+// Number of (z0, z1) partials a reduction of n leaves at `per_block` tiles
+// per block writes to its workspace (0 when it needs none).
+int64_t reduce_work_pairs(int64_t n, int64_t per_block);
 
 template <typename T>
-void run_reduce(const Launch &L, int leaf, int64_t n, const void *x0, const void *x1, const void *y0,
-                const void *y1, void *out, void *work);
+void run_reduce(const Launch &L, int leaf, int64_t n, int64_t per_block, const void *x0, const void *x1,
+                const void *y0, const void *y1, void *out, void *work);
 
 }  // namespace tf

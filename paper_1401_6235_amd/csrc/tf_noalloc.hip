@@ -50,8 +50,13 @@ extern "C" int tf_dot_noalloc(int dtype, int64_t n, const void *x0, const void *
     if (n > 0 && (x0 == nullptr || y0 == nullptr)) return TF_EINVAL;
     // every partial of every level is written before it is read, so the
     // array needs no clearing between calls
-    const int64_t pairs = reduce_work_pairs(n);
-    if (pairs > (int64_t)(TF_NOALLOC_SCRATCH_BYTES / (2 * (size_t)s))) return TF_ENOMEM;
+    const int leaf = x1 && y1 ? LEAF_DOT_TT : x1 ? LEAF_DOT_TD : y1 ? LEAF_DOT_DT : LEAF_DOT_DD;
+    const int64_t cap = (int64_t)(TF_NOALLOC_SCRATCH_BYTES / (2 * (size_t)s));
+    // more tiles per block when the partials would not fit: the tree does
+    // not depend on it
+    int64_t pb = tiles_per_block(s, leaf);
+    while (reduce_work_pairs(n, pb) > cap && pb < kMaxTilesPerBlock) pb *= 2;
+    if (reduce_work_pairs(n, pb) > cap) return TF_ENOMEM;
     hipError_t err = hipSuccess;
     void *work = scratch_address(&err);
     if (work == nullptr) return TF_EDEVICE;
@@ -61,8 +66,7 @@ extern "C" int tf_dot_noalloc(int dtype, int64_t n, const void *x0, const void *
     L.aligned = true;
     for (const void *p : {x0, x1, y0, y1}) L.aligned = L.aligned && ((uintptr_t)p & 15u) == 0;
     L.cap = 0;
-    const int leaf = x1 && y1 ? LEAF_DOT_TT : x1 ? LEAF_DOT_TD : y1 ? LEAF_DOT_DT : LEAF_DOT_DD;
-    if (dtype == TF_F64) run_reduce<double>(L, leaf, n, x0, x1, y0, y1, out, work);
-    else run_reduce<float>(L, leaf, n, x0, x1, y0, y1, out, work);
+    if (dtype == TF_F64) run_reduce<double>(L, leaf, n, pb, x0, x1, y0, y1, out, work);
+    else run_reduce<float>(L, leaf, n, pb, x0, x1, y0, y1, out, work);
     return call_status() == hipSuccess ? TF_OK : TF_EDEVICE;
 }

@@ -18,6 +18,7 @@
 //     stays in registers.
 #include "tf_tree.hpp"
 
+
 namespace tf {
 
 template <typename T>
@@ -26,14 +27,16 @@ __device__ __forceinline__ void write_out(T *out, const Pair<T> &v, bool plain) 
     if (!plain) out[1] = v.lo;
 }
 
-// Tiles -> one partial per block (or the final result when there is one).
-template <typename T, int LEAF>
-__global__ __launch_bounds__(kBlock) void reduce_tiles_kernel(int64_t n, int64_t tiles, int per_block,
-                                                              int aligned, const T *x0, const T *x1,
-                                                              const T *y0, const T *y1,
-                                                              Pair<T> *partial, T *out) {
+// Tiles -> one partial per block (or the final result when there is one),
+// blocks of WAVES waves.
+template <typename T, int LEAF, int WAVES, bool ONE_PASS>
+__global__ __launch_bounds__(64 * WAVES) void reduce_tiles_kernel(int64_t n, int64_t tiles, int per_block,
+                                                                  int aligned, const T *x0, const T *x1,
+                                                                  const T *y0, const T *y1,
+                                                                  Pair<T> *partial, T *out) {
     constexpr bool PLAIN = LeafTraits<LEAF>::plain;
-    const Pair<T> r = block_subtree<T, LEAF>(blockIdx.x, per_block, n, tiles, aligned != 0, x0, x1, y0, y1);
+    const Pair<T> r = block_subtree<T, LEAF, WAVES, ONE_PASS>(blockIdx.x, per_block, n, tiles, aligned != 0,
+                                                              x0, x1, y0, y1);
     if (threadIdx.x == 0) {
         if (out) write_out(out, r, PLAIN);
         else partial[blockIdx.x] = r;
@@ -52,17 +55,19 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(int64_t count, 
     }
 }
 
-// The last level, one block: 16 waves share the join (a quarter of the
-// chunks per wave that four waves would fold one after another), same tree.
+// The last level, one block: 16 waves share the join, each lane folding up
+// to 16 consecutive partials in registers (a whole last level of 16384
+// partials in one round of loads), same tree.
 constexpr int kWideBlock = 1024;
 template <typename T, bool PLAIN>
 __global__ __launch_bounds__(kWideBlock) void reduce_last_kernel(int64_t count, int64_t span, const Pair<T> *in,
                                                                  T *out) {
-    const Pair<T> r = block_join<T, PLAIN, kWideBlock / 64>(0, count, span, in);
+    const Pair<T> r = block_join<T, PLAIN, kWideBlock / 64, 16>(0, count, span, in);
     if (threadIdx.x == 0) write_out(out, r, PLAIN);
 }
 
-constexpr int64_t kMaxSpan = 4 * 64 * 64;  // partials one block joins
+constexpr int64_t kMaxSpan = 4 * 64 * 64;                   // partials a middle-level block joins
+constexpr int64_t kLastSpan = (kWideBlock / 64) * 64 * 64;  // partials the last-level block joins
 
 static int64_t pow2_ceil(int64_t v) {
     int64_t p = 1;
@@ -70,11 +75,37 @@ static int64_t pow2_ceil(int64_t v) {
     return p;
 }
 
-RedShape reduce_shape(int64_t n) {
+// First-pass geometry when none is configured, the fastest whole call
+// (first pass plus the joins of its partials) of a sweep on MI355X at
+// n = 2^26 over 8-128 tiles and 4, 8 or 16 waves per block:
+//   binary32, leaves from one or two arrays   32 tiles, 8 waves (one group
+//                                             of tile pairs per wave)
+//   binary32, leaves from three or four       32 tiles, 4 waves
+//   binary64, leaves from one or two arrays   64 tiles, 4 waves
+//   binary64, leaves from three or four       16 tiles, 4 waves
+static int leaf_arrays(int leaf) {
+    switch (leaf) {
+    case LEAF_SUM_D: case LEAF_PSUM: return 1;
+    case LEAF_SUM_T: case LEAF_DOT_DD: case LEAF_PDOT: return 2;
+    case LEAF_DOT_TT: return 4;
+    default: return 3;
+    }
+}
+
+static int64_t auto_tiles_per_block(int elem_size, int leaf) {
+    if (elem_size == 4) return 32;
+    return leaf_arrays(leaf) <= 2 ? 64 : 16;
+}
+
+static int auto_waves(int elem_size, int leaf) {
+    return elem_size == 4 && leaf_arrays(leaf) <= 2 ? 8 : 4;
+}
+
+RedShape reduce_shape(int64_t n, int64_t per_block) {
     RedShape s;
     s.tiles = (n + kTile - 1) / kTile;
     const int64_t P = pow2_ceil(s.tiles > 0 ? s.tiles : 1);
-    int64_t pb = config().red_tiles_per_block;
+    int64_t pb = per_block;
     if (pb > P) pb = P;
     s.per_block = pb;
     s.blocks = (s.tiles + pb - 1) / pb;
@@ -82,78 +113,113 @@ RedShape reduce_shape(int64_t n) {
     return s;
 }
 
-// Partials launch_reduce stores in the workspace for n leaves: the first
-// pass's per-block partials and every further level that is not the last.
-int64_t reduce_work_pairs(int64_t n) {
-    if (n <= 0) return 0;
-    const RedShape s = reduce_shape(n);
-    int64_t total = 0, count = s.blocks, padded = s.padded;
-    if (padded > 1) total += count;
+int64_t tiles_per_block(int elem_size, int leaf) {
+    const int64_t c = config().red_tiles_per_block;
+    return c > 0 ? c : auto_tiles_per_block(elem_size, leaf);
+}
+
+// Waves per first-pass block: the configured 4, 8 or 16, else the tuned
+// value; never more waves than tiles.
+static int reduce_waves(int elem_size, int leaf, int64_t per_block) {
+    int64_t w = config().red_waves;
+    if (w == 0) w = auto_waves(elem_size, leaf);
+    while (w > 4 && w > per_block) w /= 2;
+    return (int)w;
+}
+
+// The levels after the first pass: middle levels join kMaxSpan partials per
+// block until at most kLastSpan remain, which one last-level block joins.
+struct RedLevel {
+    int64_t count, span, next_count;
+    bool last;
+};
+template <typename F>
+static void for_each_level(const RedShape &s, F f) {
+    int64_t count = s.blocks, padded = s.padded;
     while (padded > 1) {
-        const int64_t span = padded < kMaxSpan ? padded : kMaxSpan;
+        const int64_t span = padded <= kLastSpan ? padded : kMaxSpan;
         const int64_t next_padded = padded / span;
         const int64_t next_count = (count + span - 1) / span;
-        if (next_padded > 1) total += next_count;
+        f(RedLevel{count, span, next_count, next_padded == 1});
         count = next_count;
         padded = next_padded;
     }
+}
+
+// Partials launch_reduce stores in the workspace: the first pass's
+// per-block partials and every further level that is not the last.
+int64_t reduce_work_pairs(int64_t n, int64_t per_block) {
+    if (n <= 0) return 0;
+    const RedShape s = reduce_shape(n, per_block);
+    int64_t total = s.padded > 1 ? s.blocks : 0;
+    for_each_level(s, [&](const RedLevel &l) {
+        if (!l.last) total += l.next_count;
+    });
     return total;
 }
 
+// The first pass with blocks of WAVES waves: the one-pass kernel when each
+// wave takes exactly one group of tile pairs.
+template <typename T, int LEAF, int WAVES>
+static void launch_tiles(const Launch &L, int64_t n, const RedShape &s, const T *x0, const T *x1, const T *y0,
+                         const T *y1, Pair<T> *work, T *out) {
+    constexpr bool PAIRS = TF_RED_PAIRS && LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS;
+    if (PAIRS && s.per_block == (int64_t)WAVES * PairLayout<T>::TILES)
+        tf_launch((reduce_tiles_kernel<T, LEAF, WAVES, PAIRS>), dim3((unsigned)s.blocks), dim3(64 * WAVES), 0,
+                  L.stream, n, s.tiles, (int)s.per_block, (int)L.aligned, x0, x1, y0, y1, work, out);
+    else
+        tf_launch((reduce_tiles_kernel<T, LEAF, WAVES, false>), dim3((unsigned)s.blocks), dim3(64 * WAVES), 0,
+                  L.stream, n, s.tiles, (int)s.per_block, (int)L.aligned, x0, x1, y0, y1, work, out);
+}
+
 template <typename T, int LEAF>
-static void launch_reduce(const Launch &L, int64_t n, const T *x0, const T *x1, const T *y0,
-                          const T *y1, T *out, Pair<T> *work) {
+static void launch_reduce(const Launch &L, int64_t n, int64_t per_block, const T *x0, const T *x1,
+                          const T *y0, const T *y1, T *out, Pair<T> *work) {
     constexpr bool PLAIN = LeafTraits<LEAF>::plain;
     if (n == 0) {  // empty: the partial pass over zero partials writes (+0, +0)
         tf_launch((reduce_partials_kernel<T, PLAIN>), dim3(1), dim3(kBlock), 0, L.stream,
                   (int64_t)0, (int64_t)1, (const Pair<T> *)nullptr, (Pair<T> *)nullptr, out);
         return;
     }
-    const RedShape s = reduce_shape(n);
+    const RedShape s = reduce_shape(n, per_block);
     const bool single = s.padded == 1;
-    tf_launch((reduce_tiles_kernel<T, LEAF>), dim3((unsigned)s.blocks), dim3(kBlock), 0, L.stream,
-              n, s.tiles, (int)s.per_block, (int)L.aligned, x0, x1, y0, y1, work,
-              single ? out : (T *)nullptr);
-    int64_t count = s.blocks, padded = s.padded;
+    const int waves = reduce_waves(sizeof(T), LEAF, s.per_block);
+    if (waves == 16) launch_tiles<T, LEAF, 16>(L, n, s, x0, x1, y0, y1, work, single ? out : nullptr);
+    else if (waves == 8) launch_tiles<T, LEAF, 8>(L, n, s, x0, x1, y0, y1, work, single ? out : nullptr);
+    else launch_tiles<T, LEAF, 4>(L, n, s, x0, x1, y0, y1, work, single ? out : nullptr);
     Pair<T> *src = work;
-    while (padded > 1) {
-        const int64_t span = padded < kMaxSpan ? padded : kMaxSpan;
-        const int64_t next_padded = padded / span;
-        const int64_t next_count = (count + span - 1) / span;
-        Pair<T> *dst = src + count;
-        const bool last = next_padded == 1;
-        if (last && span >= kWideBlock / 64)
-            tf_launch((reduce_last_kernel<T, PLAIN>), dim3(1), dim3(kWideBlock), 0, L.stream, count, span,
+    for_each_level(s, [&](const RedLevel &l) {
+        Pair<T> *dst = src + l.count;
+        if (l.last && l.span >= kWideBlock / 64)
+            tf_launch((reduce_last_kernel<T, PLAIN>), dim3(1), dim3(kWideBlock), 0, L.stream, l.count, l.span,
                       (const Pair<T> *)src, out);
         else
-            tf_launch((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)next_count), dim3(kBlock), 0,
-                      L.stream, count, span, (const Pair<T> *)src, dst, last ? out : (T *)nullptr);
+            tf_launch((reduce_partials_kernel<T, PLAIN>), dim3((unsigned)l.next_count), dim3(kBlock), 0,
+                      L.stream, l.count, l.span, (const Pair<T> *)src, dst, l.last ? out : (T *)nullptr);
         src = dst;
-        count = next_count;
-        padded = next_padded;
-    }
+    });
 }
 
 template <typename T>
-void run_reduce(const Launch &L, int leaf_kind, int64_t n, const void *x0, const void *x1,
+void run_reduce(const Launch &L, int leaf_kind, int64_t n, int64_t per_block, const void *x0, const void *x1,
                 const void *y0, const void *y1, void *out, void *work) {
     const T *a0 = (const T *)x0, *a1 = (const T *)x1, *b0 = (const T *)y0, *b1 = (const T *)y1;
     T *o = (T *)out;
     Pair<T> *w = (Pair<T> *)work;
     switch (leaf_kind) {
-    case LEAF_SUM_D: launch_reduce<T, LEAF_SUM_D>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_SUM_T: launch_reduce<T, LEAF_SUM_T>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_DOT_DD: launch_reduce<T, LEAF_DOT_DD>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_DOT_TT: launch_reduce<T, LEAF_DOT_TT>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_DOT_TD: launch_reduce<T, LEAF_DOT_TD>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_DOT_DT: launch_reduce<T, LEAF_DOT_DT>(L, n, a0, a1, b0, b1, o, w); break;
-    case LEAF_PSUM: launch_reduce<T, LEAF_PSUM>(L, n, a0, a1, b0, b1, o, w); break;
-    default: launch_reduce<T, LEAF_PDOT>(L, n, a0, a1, b0, b1, o, w); break;
+    case LEAF_SUM_D: launch_reduce<T, LEAF_SUM_D>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_SUM_T: launch_reduce<T, LEAF_SUM_T>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_DOT_DD: launch_reduce<T, LEAF_DOT_DD>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_DOT_TT: launch_reduce<T, LEAF_DOT_TT>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_DOT_TD: launch_reduce<T, LEAF_DOT_TD>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_DOT_DT: launch_reduce<T, LEAF_DOT_DT>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    case LEAF_PSUM: launch_reduce<T, LEAF_PSUM>(L, n, per_block, a0, a1, b0, b1, o, w); break;
+    default: launch_reduce<T, LEAF_PDOT>(L, n, per_block, a0, a1, b0, b1, o, w); break;
     }
 }
-template void run_reduce<double>(const Launch &, int, int64_t, const void *, const void *, const void *,
-                                 const void *, void *, void *);
-template void run_reduce<float>(const Launch &, int, int64_t, const void *, const void *, const void *,
-                                const void *, void *, void *);
+template void run_reduce<double>(const Launch &, int, int64_t, int64_t, const void *, const void *,
+                                 const void *, const void *, void *, void *);
+template void run_reduce<float>(const Launch &, int, int64_t, int64_t, const void *, const void *,
+                                const void *, const void *, void *, void *);
 
 }  // namespace tf

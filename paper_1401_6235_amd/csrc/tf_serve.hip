@@ -392,7 +392,7 @@ template <typename T>
 __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done *rec) {
     tfs_done out = {};
     if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
-        // four chunks in flight: the serving kernel's register budget is set
+        // four partials per lane in flight: the serving kernel's register budget is set
         // by its largest path, and two waves per SIMD must fit
         const Pair<T> r = block_join<T, false, 4, 4>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
         const double z0 = (double)r.hi, z1 = (double)r.lo;

@@ -269,13 +269,13 @@ struct PairLayout {
     __device__ static int slot(int v) { return TF_RED_LDS_PAD ? v + v / VPL : v; }
 };
 
-// One LDS region per kernel, shared by every instantiation (4 waves, sized
-// for the larger of the two layouts).
+// One LDS region per kernel and block size, shared by every instantiation
+// (one region per wave, sized for the larger of the two layouts).
 constexpr int kPairSlots = PairLayout<double>::SLOTS > PairLayout<float>::SLOTS ? PairLayout<double>::SLOTS
                                                                                 : PairLayout<float>::SLOTS;
-constexpr int kPairLdsBytes = 4 * kPairSlots * 16;
+template <int WAVES>
 __device__ __forceinline__ void *pair_lds_base() {
-    __shared__ __attribute__((aligned(16))) unsigned char buf[kPairLdsBytes];
+    __shared__ __attribute__((aligned(16))) unsigned char buf[WAVES * kPairSlots * 16];
     return buf;
 }
 
@@ -412,18 +412,23 @@ __device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
 }
 
 // Value of the aligned subtree of `per_block` tiles (a power of two, at most
-// 64 * 4) that starts at tile b * per_block, computed by one block of 4
-// waves; valid in thread 0.  Each wave takes per_block / 4 consecutive tiles
-// (or one); lane t keeps the value of the wave's tile t, and a butterfly over
-// those lanes gives the wave's subtree.  Tiles at or beyond `tiles` are
-// (+0, +0).  Contains __syncthreads: call from every thread.
-template <typename T, int LEAF>
+// 64 * WAVES) that starts at tile b * per_block, computed by one block of
+// WAVES waves; valid in thread 0.  Each wave takes per_block / WAVES
+// consecutive tiles (or one); lane t keeps the value of the wave's tile t,
+// and a butterfly over those lanes gives the wave's subtree.  Tiles at or
+// beyond `tiles` are (+0, +0).  Contains __syncthreads: call from every
+// thread.
+// ONE_PASS: every wave reduces exactly one group of tile pairs (per_block ==
+// WAVES * PairLayout<T>::TILES, leaves from at most two arrays); the
+// pipelined loop and its second buffer are left out, which frees registers
+// for more waves per SIMD.
+template <typename T, int LEAF, int WAVES = 4, bool ONE_PASS = false>
 __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64_t n, int64_t tiles,
                                                  bool aligned, const T *x0, const T *x1, const T *y0,
                                                  const T *y1) {
     constexpr bool PLAIN = LeafTraits<LEAF>::plain;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int per_wave = per_block >= 4 ? per_block / 4 : 1;
+    const int per_wave = per_block >= WAVES ? per_block / WAVES : 1;
     const int waves = per_block / per_wave;
     Pair<T> mine{T(0), T(0)};
 #if TF_RED_PAIRS
@@ -435,8 +440,22 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
     using PL = PairLayout<T>;
     if (LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS && per_wave >= PL::TILES) {  // per_wave: a power of two
         typename Vec<T>::type *lds =
-            reinterpret_cast<typename Vec<T>::type *>(pair_lds_base()) + wave * PL::SLOTS;
+            reinterpret_cast<typename Vec<T>::type *>(pair_lds_base<WAVES>()) + wave * PL::SLOTS;
         const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
+        if constexpr (ONE_PASS) {
+            if (t0 < tiles) {
+                PairData<T> cur;
+                pair_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
+                const Pair<T> v = pair_reduce<T, LEAF>(cur, lds);
+#pragma unroll
+                for (int q = 0; q < PL::TILES; ++q) {
+                    const Pair<T> val{readlane_t(v.hi, q * PL::LANES), readlane_t(v.lo, q * PL::LANES)};
+                    if (lane == q && t0 + q < tiles) mine = val;
+                }
+            }
+            mine = butterfly_m<T, PLAIN>(mine, lane, PL::TILES);
+            return join_waves<T, PLAIN, WAVES>(mine, waves);
+        }
         // the next group's loads are in flight while the current one is reduced
         PairData<T> cur, nxt;
         if (t0 < tiles) pair_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
@@ -455,7 +474,7 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
             cur = nxt;
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
-        return join_waves<T, PLAIN>(mine, waves);
+        return join_waves<T, PLAIN, WAVES>(mine, waves);
     }
 #endif
     if (wave < waves) {
@@ -476,44 +495,52 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
     }
-    return join_waves<T, PLAIN>(mine, waves);
+    return join_waves<T, PLAIN, WAVES>(mine, waves);
 }
 
 // Join of the aligned group of `span` partials (a power of two, at most
 // WAVES * 64 * 64) starting at b * span; partials at index >= count are
-// (+0, +0).  Each of the block's WAVES waves folds span / WAVES consecutive
-// partials (or one) in chunks of 64 lanes, lane j keeping chunk j, GROUP
-// chunks' loads at a time; the tree is the same for any WAVES and GROUP.
-// Valid in thread 0.  Call from every thread.
-template <typename T, bool PLAIN, int WAVES = 4, int GROUP = 64 / WAVES>
+// (+0, +0).  Each of the block's WAVES waves takes span / WAVES consecutive
+// partials (or one) and folds them in chunks of 64 K: lane l loads K
+// consecutive partials of the chunk (K a power of two, at most KMAX) and
+// forms their subtree in registers, a butterfly joins the 64 lanes, and lane
+// j keeps chunk j until a last butterfly joins the chunks.  Every subtree is
+// aligned, so the tree is the same for any WAVES and KMAX.  Valid in thread
+// 0.  Call from every thread.
+template <typename T, bool PLAIN, int WAVES = 4, int KMAX = 8>
 __device__ __forceinline__ Pair<T> block_join(int64_t b, int64_t count, int64_t span, const Pair<T> *in) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t per_wave = span >= WAVES ? span / WAVES : 1;
     const int waves = (int)(span / per_wave);
     Pair<T> mine{T(0), T(0)};
-    if (wave < waves) {
+    if (wave < waves && count > 0) {  // count == 0: every partial is zero (and `in` may be NULL)
         const int64_t first = b * span + (int64_t)wave * per_wave;
-        const int64_t width = per_wave < 64 ? per_wave : 64;
-        const int64_t chunks = per_wave / width;
-        // Chunks of 64 partials, reduced in groups of kGroup whose loads are
-        // all issued before the first butterfly (one memory round trip per
-        // group instead of one per chunk); each chunk's tree is unchanged.
-        constexpr int kGroup = GROUP;  // chunks whose loads are in flight together
-        for (int64_t j0 = 0; j0 < chunks; j0 += kGroup) {
-            Pair<T> v[kGroup];
+        const int64_t width = per_wave < 64 ? per_wave : 64;  // lanes per chunk
+        const int64_t runs = per_wave / width;                 // partials per lane over the wave
+        const int K = runs < KMAX ? (int)runs : KMAX;
+        const int64_t chunk = width * K;
+        const int64_t chunks = per_wave / chunk;
+        for (int64_t j = 0; j < chunks; ++j) {
+            const int64_t base = first + j * chunk + (int64_t)lane * K;
+            // every load is issued (an absent partial reads partial 0 and is
+            // replaced by zero), so all KMAX are in flight together
+            Pair<T> v[KMAX];
 #pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                const int64_t i = first + (j0 + g) * width + lane;
-                v[g] = (j0 + g < chunks && lane < width && i < count) ? in[i] : Pair<T>{T(0), T(0)};
+            for (int q = 0; q < KMAX; ++q) {
+                const int64_t i = base + q;
+                const bool ok = q < K && lane < width && i < count;
+                const Pair<T> p = in[ok ? i : 0];
+                v[q] = ok ? p : Pair<T>{T(0), T(0)};
             }
 #pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                if (j0 + g < chunks) {
-                    const Pair<T> r = butterfly_m<T, PLAIN>(v[g], lane, (int)width);
-                    if (lane == j0 + g) mine = r;
-                    if (chunks == 1) mine = r;
+            for (int w = KMAX; w > 1; w >>= 1) {
+                if (w <= K) {
+#pragma unroll
+                    for (int q = 0; q < w / 2; ++q) v[q] = node<T, PLAIN>(v[2 * q], v[2 * q + 1]);
                 }
             }
+            const Pair<T> r = butterfly_m<T, PLAIN>(v[0], lane, (int)width);
+            if (lane == j || chunks == 1) mine = r;
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, (int)chunks);
     }

@@ -21,7 +21,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtfgen.so")
+# TF_WORKLOADS_LIB selects another build of the library (the sanitizer tests use it)
+LIB_PATH = os.environ.get("TF_WORKLOADS_LIB") or os.path.join(_HERE, "libtfgen.so")
 SOURCE = os.path.join(_HERE, "illdot.c")
 
 # Stream keys (first element of the spawn key).

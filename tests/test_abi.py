@@ -50,6 +50,9 @@ def test_host_only_calls():
     assert lib.tf_mul(tf.TF_F32, ctypes.c_int64(0), None, None, None, None, None, None, None) == 0
     # tuning knobs validate their values
     assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(3)) == -1
+    assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(512)) == -1
+    assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(-1)) == -1
+    assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(0)) == 0  # default: tuned (0)
     assert lib.tf_config(99, ctypes.c_int64(1)) == -1
     # the chain, coupled and application calls validate op, mode and sizes
     i64 = ctypes.c_int64
@@ -64,7 +67,7 @@ def test_host_only_calls():
     assert lib.tf_fma(tf.TF_F32, i64(0), *([None] * 8), None) == 0
     # the allocation-free dot validates its arguments and rejects, on the
     # host and before any device call, partials beyond its static array
-    # (2^40 leaves need 2^26 partials at the default tiling)
+    # (2^40 leaves leave 2^24 partials even at 256 tiles per block)
     dummy = ctypes.c_void_p(256)
     assert lib.tf_dot_noalloc(7, i64(10), dummy, None, dummy, None, dummy, None) == -1
     assert lib.tf_dot_noalloc(tf.TF_F64, i64(-1), dummy, None, dummy, None, dummy, None) == -1

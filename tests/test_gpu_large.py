@@ -5,12 +5,14 @@ that size.
 Inputs are seeded on the device with torch's generator (sign-uniform high
 parts in [0.5, 1.5), low parts about one unit in the last place); the
 oracle recomputes sampled elements, including the ones around 2^31 and the
-ragged tail.  For the sum the oracle cannot afford 2^31 leaves, so the test
-uses the tree's shape instead: with n = 2^31 + m the root joins the first
-2^31 leaves (an exact power of two of tiles, no padding) with the rest,
-whose subtree is the tail's own tree joined with zero subtrees, and
-ATF1(v, (+0, +0)) = v.  So the whole sum must equal ATF1 of the library's
-sums of the two parts, computed by the oracle.
+ragged tail.  The sum is checked three ways: the 1000003-leaf tail's sum
+against the oracle; the whole sum against the oracle run on the host over
+all 2^31 + 1000003 leaves (16 or 32 GiB of host memory, when available);
+and the tree's shape: with n = 2^31 + m the root joins the first 2^31
+leaves (an exact power of two of tiles, no padding) with the rest, whose
+subtree is the tail's own tree joined with zero subtrees, and
+ATF1(v, (+0, +0)) = v, so the whole sum must equal ATF1 of the library's
+sums of the two parts.
 """
 import numpy as np
 import pytest
@@ -77,6 +79,7 @@ def test_add_past_2e31_elements(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_sum_past_2e31_elements(dtype):
+    import psutil
     torch = torch_cuda()
     torch.cuda.empty_cache()  # memory cached by earlier tests
     free, _ = torch.cuda.mem_get_info()
@@ -89,8 +92,25 @@ def test_sum_past_2e31_elements(dtype):
     half = 1 << 31
     left = tf.tf_sum(x0[:half], x1[:half]).cpu().numpy()
     right = tf.tf_sum(x0[half:].contiguous(), x1[half:].contiguous()).cpu().numpy()
-    del x0, x1
-    torch.cuda.empty_cache()
+    # the 1000003-leaf tail straight against the oracle
+    step("tail sum %s against the oracle" % dtype)
+    tail = [t[half:].cpu().numpy() for t in (x0, x1)]
+    assert_bits(right, np.array(oracle.sum(*tail)), "tail sum")
+    del tail
+    # the whole sum against the oracle on the host, when the host holds both
+    # arrays (16 or 32 GiB); otherwise the decomposition below stands alone
+    es = 4 if dtype == "f32" else 8
+    host_need = 2 * N_BIG * es + 4 * GIB
+    if psutil.virtual_memory().available > host_need:
+        step("whole sum %s against the oracle on the host" % dtype)
+        xh = [t.cpu().numpy() for t in (x0, x1)]
+        del x0, x1
+        torch.cuda.empty_cache()
+        assert_bits(whole, np.array(oracle.sum(*xh)), "whole sum")
+        del xh
+    else:
+        del x0, x1
+        torch.cuda.empty_cache()
     assert right[0] != 0 and right[1] != 0  # ATF1(v, 0) = v needs no signed-zero low part
     want = oracle.add(left[:1], left[1:], right[:1], right[1:])
     assert_bits(whole[:1], want[0], "sum z0")

@@ -72,7 +72,7 @@ def test_every_block_geometry_gives_the_same_bits(dtype):
     n = 3 * (1 << 18) + 77
     case = random_case(n, dtype, 99)
     want = oracle_all(*case)
-    for tpb in (1, 2, 4, 8, 16, 32, 64):
+    for tpb in (1, 2, 4, 8, 16, 32, 64, 128, 256):
         step("geometry tiles/block=%d %s" % (tpb, np.dtype(dtype)))
         old = tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, tpb)
         try:

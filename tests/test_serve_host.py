@@ -3,8 +3,9 @@
 tests/serve_host/fake_device.cpp drives the library's server (admission,
 pool, descriptor ring, completion handling from tf_serve_host.hpp) with a
 thread in place of the persistent kernel, and prints one JSON line per
-scenario.  Built with g++ (host code only), once plainly and once under
-ThreadSanitizer.
+scenario.  Built with g++ (host code only): plainly, under ThreadSanitizer,
+and under AddressSanitizer with UndefinedBehaviorSanitizer (leak checks
+on).
 """
 import json
 import os
@@ -65,4 +66,13 @@ def test_server_host_logic_under_thread_sanitizer(tmp_path):
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
     res, err = run(exe, env)
     assert "ThreadSanitizer" not in err, err[:4000]
+    check(res)
+
+
+def test_server_host_logic_under_address_and_undefined_sanitizers(tmp_path):
+    exe = build(tmp_path, ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"])
+    env = dict(os.environ, ASAN_OPTIONS="halt_on_error=1:detect_leaks=1:exitcode=66",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1:exitcode=67")
+    res, err = run(exe, env)
+    assert "AddressSanitizer" not in err and "runtime error" not in err and "LeakSanitizer" not in err, err[:4000]
     check(res)

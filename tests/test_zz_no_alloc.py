@@ -2,8 +2,9 @@
 against tf_dot (caller workspace), bit for bit, through the C ABI.
 
 Two calls in a row on one stream, the second smaller, for every leaf kind
-and both types; a size whose partials take two levels; n = 0; and the
-rejection of a size whose partials do not fit.  Run after the other GPU
+and both types; a size whose partials take two levels; n = 0; a tiling
+whose partials would not fit (the call adapts it); and the rejection of a
+size whose partials cannot fit.  Run after the other GPU
 tests and alone in a fresh process, it must pass either way.
 """
 import ctypes
@@ -65,7 +66,7 @@ def test_two_calls_in_a_row_match_tf_dot(kind, dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_two_level_partials_then_small(dtype):
-    """n past 2^28 leaves: the first pass leaves more than 16384 partials, so
+    """n past 2^28 leaves: the first pass leaves more than 65536 partials, so
     a middle level is stored in the array too; then a small call."""
     torch = torch_cuda()
     td = torch.float64 if dtype == np.float64 else torch.float32
@@ -99,33 +100,30 @@ def test_empty_writes_zero(dtype):
     assert_bits(to_np(out), np.zeros(2, dtype=dtype), "n=0")
 
 
-def test_rejects_partials_that_do_not_fit():
-    """With one tile per block, 2^27 binary64 leaves need 2^19 partials of 16
-    bytes (8 MiB): rejected on the host before any launch; at the default
-    tiling the same size fits."""
+def test_tiling_adapts_then_rejects():
+    """With one tile per block configured, 2^27 binary64 leaves would leave
+    2^19 partials of 16 bytes (8 MiB): the call takes more tiles per block
+    instead and still matches tf_dot bit for bit.  2^36 leaves leave too many
+    partials even at 256 tiles per block: rejected on the host before any
+    launch (the pointers are never read)."""
     torch = torch_cuda()
     lib = tf.lib()
-    small = torch.zeros(4, dtype=torch.float64, device="cuda")
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
-    p = ctypes.c_void_p(small.data_ptr())
-    old = tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, 1)
-    try:
-        st = lib.tf_dot_noalloc(tf.TF_F64, ctypes.c_int64(1 << 27), p, None, p, None,
-                                ctypes.c_void_p(out.data_ptr()), None)
-    finally:
-        tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, old)
-    assert st == -3  # TF_ENOMEM
-    # through the binding: the same rejection raises (inputs never read)
     big = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    big.fill_(0.5)
+    big[1::3] = -0.25
+    step("noalloc n=2^27 binary64 at one tile per block")
     old = tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, 1)
     try:
-        with pytest.raises(tf.TwofoldError, match="tf_dot_noalloc"):
-            tf.tf_dot_noalloc(big, None, big, None, out)
+        got = to_np(tf.tf_dot_noalloc(big, None, big, None, out))
+        want = to_np(tf.tf_dot(big, None, big, None))
     finally:
         tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, old)
-    # at the default tiling the same size fits
-    big.fill_(0.5)
-    got = tf.tf_dot_noalloc(big, None, big, None, out)
-    assert_bits(to_np(got), to_np(tf.tf_dot(big, None, big, None)), "n=2^27 at the default tiling")
+    assert_bits(got, want, "n=2^27 at one tile per block")
+    step("noalloc rejection of n=2^36")
+    p = ctypes.c_void_p(big.data_ptr())
+    st = lib.tf_dot_noalloc(tf.TF_F64, ctypes.c_int64(1 << 36), p, None, p, None,
+                            ctypes.c_void_p(out.data_ptr()), None)
+    assert st == -3  # TF_ENOMEM
     del big
     torch.cuda.empty_cache()
