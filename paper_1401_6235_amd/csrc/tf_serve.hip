@@ -227,6 +227,18 @@ __device__ void dispatcher(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
     st_rel_sys(&sh->kernel_state, (uint64_t)how);
 }
 
+// Reduction units with the next tile group's loads in flight while the
+// current one is reduced (1) or each loaded when reached (0, fewer
+// registers).
+#ifndef TF_SERVE_RED_PIPE
+#define TF_SERVE_RED_PIPE 1
+#endif
+
+// Vectors per operand and thread in flight in a vector unit.
+#ifndef TF_SERVE_VEC_GROUP
+#define TF_SERVE_VEC_GROUP 4
+#endif
+
 // ---- one unit of a reduction job ---------------------------------------------
 
 template <typename T, int LEAF>
@@ -234,7 +246,8 @@ __device__ void claim_reduce(const tfs_desc &d, int claim) {
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
     const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1) & 15u) == 0;
     const int64_t tiles = (d.n + kTile - 1) / kTile;
-    const Pair<T> r = block_subtree<T, LEAF>(claim, d.tiles_per_claim, d.n, tiles, aligned, x0, x1, y0, y1);
+    const Pair<T> r = block_subtree<T, LEAF, 4, false, TF_SERVE_RED_PIPE>(claim, d.tiles_per_claim, d.n, tiles,
+                                                                          aligned, x0, x1, y0, y1);
     if (threadIdx.x == 0) ((Pair<T> *)d.part)[claim] = r;
 }
 
@@ -299,15 +312,16 @@ __device__ __forceinline__ Pair<T> vector_elem(const tfs_desc &d, T a0, T a1, T 
     else return horner_desc<T, XT>(d.c, d.degree, x0, x1);
 }
 
-// TFS_CLAIM elements: 16 per thread as 16-byte vectors, four vectors per
-// operand in flight, consecutive threads on consecutive vectors; a short
+
+// TFS_CLAIM elements: 16 per thread as 16-byte vectors, TF_SERVE_VEC_GROUP
+// vectors per operand in flight, consecutive threads on consecutive vectors; a short
 // or misaligned unit takes a scalar loop.
 template <typename T, int OP, bool XT, bool YT>
 __device__ void claim_vector(const tfs_desc &d, int claim) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     constexpr int NV = TFS_CLAIM / kBlock / W;  // vectors per thread
-    constexpr int U = NV < 4 ? NV : 4;
+    constexpr int U = NV < TF_SERVE_VEC_GROUP ? NV : TF_SERVE_VEC_GROUP;
     constexpr bool HAS_Y = OP == TFS_OP_AXPY;
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
     T *z0 = (T *)d.z0, *z1 = (T *)d.z1;
@@ -330,17 +344,44 @@ __device__ void claim_vector(const tfs_desc &d, int claim) {
                 if constexpr (HAS_Y) q0[u] = vload(y0, i);
                 if constexpr (HAS_Y && YT) q1[u] = vload(y1, i);
             }
+            Pair<T> z[U][W];
+            if constexpr (OP == TFS_OP_HORNER) {
+                // the U * W elements' Horner steps interleaved (degree loop
+                // outside), each element's operations unchanged: one wave per
+                // SIMD then has independent chains to issue
+                const T cd = (T)d.c[d.degree];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < W; ++k) z[u][k] = Pair<T>{cd, T(0)};
+                for (int j = d.degree - 1; j >= 0; --j) {
+                    const T cj = (T)d.c[j];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int k = 0; k < W; ++k) {
+                            const Pair<T> m = XT ? mul_tt(z[u][k].hi, z[u][k].lo, p0[u][k], p1[u][k])
+                                                 : mul_td(z[u][k].hi, z[u][k].lo, p0[u][k]);
+                            z[u][k] = add_td(m.hi, m.lo, cj);
+                        }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        z[u][k] = vector_elem<T, OP, XT, YT>(d, a0, a1, p0[u][k], XT ? p1[u][k] : T(0),
+                                                             HAS_Y ? q0[u][k] : T(0),
+                                                             (HAS_Y && YT) ? q1[u][k] : T(0));
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 V r0, r1;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    const Pair<T> z = vector_elem<T, OP, XT, YT>(d, a0, a1, p0[u][k], XT ? p1[u][k] : T(0),
-                                                                HAS_Y ? q0[u][k] : T(0),
-                                                                (HAS_Y && YT) ? q1[u][k] : T(0));
-                    r0[k] = z.hi;
-                    r1[k] = z.lo;
-                    account(acc, z.hi, z.lo, d.thr);
+                    r0[k] = z[u][k].hi;
+                    r1[k] = z[u][k].lo;
+                    account(acc, z[u][k].hi, z[u][k].lo, d.thr);
                 }
                 const int64_t i = vb + (int64_t)(j0 + u) * kBlock + t;
                 vstore(z0, i, r0);
@@ -594,7 +635,10 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void serve_kernel(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
+// Every worker block must be resident: with k worker blocks of 256 threads
+// per CU each SIMD holds k waves, so the registers are capped for k.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_SERVE_WORKERS_PER_CU)))
+void serve_kernel(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) dispatcher(sh, st, idle_ticks);
         return;

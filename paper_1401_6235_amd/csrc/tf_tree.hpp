@@ -421,8 +421,10 @@ __device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
 // ONE_PASS: every wave reduces exactly one group of tile pairs (per_block ==
 // WAVES * PairLayout<T>::TILES, leaves from at most two arrays); the
 // pipelined loop and its second buffer are left out, which frees registers
-// for more waves per SIMD.
-template <typename T, int LEAF, int WAVES = 4, bool ONE_PASS = false>
+// for more waves per SIMD.  PIPE = false keeps the loop but not the second
+// buffer (each group or tile loaded when it is reached), for callers whose
+// register budget is tight.
+template <typename T, int LEAF, int WAVES = 4, bool ONE_PASS = false, bool PIPE = true>
 __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64_t n, int64_t tiles,
                                                  bool aligned, const T *x0, const T *x1, const T *y0,
                                                  const T *y1) {
@@ -456,6 +458,23 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
             mine = butterfly_m<T, PLAIN>(mine, lane, PL::TILES);
             return join_waves<T, PLAIN, WAVES>(mine, waves);
         }
+        if constexpr (!PIPE) {
+            for (int p = 0; PL::TILES * p < per_wave; ++p) {
+                const int64_t tile = t0 + PL::TILES * p;
+                if (tile < tiles) {
+                    PairData<T> cur;
+                    pair_load<T, LEAF>(cur, tile, n, aligned, x0, x1, y0, y1);
+                    const Pair<T> v = pair_reduce<T, LEAF>(cur, lds);
+#pragma unroll
+                    for (int q = 0; q < PL::TILES; ++q) {
+                        const Pair<T> val{readlane_t(v.hi, q * PL::LANES), readlane_t(v.lo, q * PL::LANES)};
+                        if (lane == PL::TILES * p + q && tile + q < tiles) mine = val;
+                    }
+                }
+            }
+            mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
+            return join_waves<T, PLAIN, WAVES>(mine, waves);
+        }
         // the next group's loads are in flight while the current one is reduced
         PairData<T> cur, nxt;
         if (t0 < tiles) pair_load<T, LEAF>(cur, t0, n, aligned, x0, x1, y0, y1);
@@ -477,7 +496,19 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
         return join_waves<T, PLAIN, WAVES>(mine, waves);
     }
 #endif
-    if (wave < waves) {
+    if (!PIPE && wave < waves) {
+        const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
+        for (int t = 0; t < per_wave; ++t) {
+            const int64_t tile = t0 + t;
+            if (tile < tiles) {
+                TileData<T> cur;
+                tile_load<T, LEAF>(cur, tile, n, aligned, x0, x1, y0, y1);
+                const Pair<T> v = tile_reduce<T, LEAF>(cur);
+                if (lane == t) mine = v;
+            }
+        }
+        mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
+    } else if (wave < waves) {
         const int64_t t0 = b * per_block + (int64_t)wave * per_wave;
         // software pipeline: the next tile's loads are in flight while the
         // current tile is reduced
