@@ -495,7 +495,7 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
 #define TF_SERVE_WORKERS_PER_CU 1
 #endif
 #ifndef TF_SERVE_BATCH_SHARE
-#define TF_SERVE_BATCH_SHARE 100  // percent of a fair share of the remaining units per claim
+#define TF_SERVE_BATCH_SHARE 400  // percent of a fair share of the remaining units per claim
 #endif
 #ifndef TF_SERVE_IDLE_SLEEP
 #define TF_SERVE_IDLE_SLEEP 127  // s_sleep units (64 cycles) between scans of an idle worker

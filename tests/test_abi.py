@@ -53,6 +53,10 @@ def test_host_only_calls():
     assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(512)) == -1
     assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(-1)) == -1
     assert lib.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, ctypes.c_int64(0)) == 0  # default: tuned (0)
+    assert lib.tf_config(tf.TF_CFG_RED_WAVES, ctypes.c_int64(2)) == -1
+    assert lib.tf_config(tf.TF_CFG_RED_WAVES, ctypes.c_int64(32)) == -1
+    assert lib.tf_config(tf.TF_CFG_RED_WAVES, ctypes.c_int64(8)) == 0
+    assert lib.tf_config(tf.TF_CFG_RED_WAVES, ctypes.c_int64(0)) == 8
     assert lib.tf_config(99, ctypes.c_int64(1)) == -1
     # the chain, coupled and application calls validate op, mode and sizes
     i64 = ctypes.c_int64

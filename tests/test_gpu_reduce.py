@@ -72,15 +72,21 @@ def test_every_block_geometry_gives_the_same_bits(dtype):
     n = 3 * (1 << 18) + 77
     case = random_case(n, dtype, 99)
     want = oracle_all(*case)
-    for tpb in (1, 2, 4, 8, 16, 32, 64, 128, 256):
-        step("geometry tiles/block=%d %s" % (tpb, np.dtype(dtype)))
+    # tiles per block at the tuned waves, then every wave count (4, 8, 16;
+    # the one-pass kernel where each wave takes exactly one tile group)
+    geometries = [(tpb, 0) for tpb in (1, 2, 4, 8, 16, 32, 64, 128, 256)]
+    geometries += [(tpb, wv) for wv in (4, 8, 16) for tpb in (8, 16, 32, 64, 256)]
+    for tpb, wv in geometries:
+        step("geometry tiles/block=%d waves=%d %s" % (tpb, wv, np.dtype(dtype)))
         old = tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, tpb)
+        old_w = tf.tf_config(tf.TF_CFG_RED_WAVES, wv)
         try:
             got = gpu_all(*case)
         finally:
             tf.tf_config(tf.TF_CFG_RED_TILES_PER_BLOCK, old)
+            tf.tf_config(tf.TF_CFG_RED_WAVES, old_w)
         for k in want:
-            assert_bits(got[k], want[k], "%s tpb=%d" % (k, tpb))
+            assert_bits(got[k], want[k], "%s tpb=%d waves=%d" % (k, tpb, wv))
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
