@@ -491,7 +491,9 @@ def bench_key(name: str):
     if t is None:
         return None
     m = re.search(r"ew_vec_kernel<\w+, (\d), true, (true|false)", name)
-    if m and m.group(1) in _OPS:
+    # both operands twofold (the square root: its one operand); the dotted
+    # forms timed outside the step launch the same kernels' other variants
+    if m and m.group(1) in _OPS and (m.group(2) == "true") == (m.group(1) != "4"):
         return "%s_%s" % (_OPS[m.group(1)], t)
     if "axpy_vec_kernel" in name and "true, true" in name:
         return "axpy_" + t
@@ -647,6 +649,64 @@ def summarize_profiles(prof_dir: str, command: str):
     json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
     if os.path.isdir(os.path.join(prof_dir, "valu64")) and os.path.isdir(os.path.join(prof_dir, "valu32")):
         summarize_valu(prof_dir, command, rows)
+    summarize_memory(prof_dir, command)
+
+
+# Memory-pipeline counter sets (one rocprofv3 --pmc run each, directories
+# mem1 .. mem5), within the per-block limits of one pass.
+MEM_SETS = [
+    "TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum TCC_EA0_WRREQ_DRAM_CREDIT_STALL_sum",
+    "TCC_TAG_STALL_sum TCC_TOO_MANY_EA_WRREQS_STALL_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_RDREQ_128B_sum",
+    "TCP_TCC_READ_REQ_LATENCY_sum TCP_TCC_READ_REQ_sum TCP_TCC_WRITE_REQ_LATENCY_sum TCP_TCC_WRITE_REQ_sum",
+    "TA_BUSY_avr TA_ADDR_STALLED_BY_TC_CYCLES_sum TD_TC_STALL_sum TD_TD_BUSY_sum TCP_UTCL1_TRANSLATION_MISS_sum "
+    "TCP_PENDING_STALL_CYCLES_sum TCP_TCR_TCP_STALL_CYCLES_sum GRBM_GUI_ACTIVE",
+    "SQ_WAIT_ANY SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAVES SQ_INST_LEVEL_VMEM "
+    "SQ_WAIT_INST_ANY",
+]
+
+
+def summarize_memory(prof_dir: str, command: str):
+    """profiles/hot_path_step_n2e28_memory_counters.txt from the MEM_SETS
+    runs: per streaming kernel of the step, requests to HBM, the L1's
+    average read / write latency to the L2, stalls of the texture addresser
+    by the L1, L2 tag stalls, DRAM credit stalls and address-translation
+    misses, each per KiB moved, and the kernel's cycles per MiB."""
+    import csv
+    import glob
+    acc = {}
+    for i in range(1, len(MEM_SETS) + 1):
+        f = glob.glob(os.path.join(prof_dir, "mem%d" % i, "*counter_collection.csv"))
+        if not f:
+            return
+        for k, (_, ds) in _bench_dispatches(csv.DictReader(open(f[0])), "Kernel_Name", "Grid_Size").items():
+            for r in ds:
+                acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    c = {k: {n: sum(v) / len(v) for n, v in d.items()} for k, d in acc.items()}
+    keys = [k for k in ("add_f64", "sub_f64", "mul_f64", "div_f64", "axpy_f64", "vmem_f64",
+                        "add_f32", "sub_f32", "mul_f32", "div_f32", "axpy_f32", "vmem_f32") if k in c]
+    lines = ["# Memory pipeline of the step's streaming kernels (n = 2^28), from rocprofv3 --pmc runs of",
+             *["#   " + m for m in MEM_SETS],
+             "# per dispatch: cycles per MiB moved (GRBM_GUI_ACTIVE), HBM read / write requests per KiB,",
+             "# average L1 -> L2 read and write latency in cycles, and per KiB: texture-addresser cycles",
+             "# stalled by the L1, L2 tag stalls, DRAM read / write credit stalls, address-translation misses",
+             "# command: " + command, "# source hash: " + kernel_source_hash(),
+             "%-10s %9s %7s %7s %8s %8s %9s %8s %8s %8s %8s" % (
+                 "bench_key", "cyc/MiB", "rd/KiB", "wr/KiB", "rd_lat", "wr_lat", "ta_stall", "tag_stl",
+                 "dram_rd", "dram_wr", "tlb_miss")]
+    for k in keys:
+        d = c[k]
+        kib = alg_bytes(k) / 1024.0
+        g = lambda n: d.get(n, float("nan"))
+        lines.append("%-10s %9.0f %7.3f %7.3f %8.0f %8.0f %9.4f %8.4f %8.4f %8.4f %8.5f" % (
+            k, g("GRBM_GUI_ACTIVE") / (kib / 1024.0), g("TCC_EA0_RDREQ_sum") / kib, g("TCC_EA0_WRREQ_sum") / kib,
+            g("TCP_TCC_READ_REQ_LATENCY_sum") / g("TCP_TCC_READ_REQ_sum"),
+            g("TCP_TCC_WRITE_REQ_LATENCY_sum") / g("TCP_TCC_WRITE_REQ_sum"),
+            g("TA_ADDR_STALLED_BY_TC_CYCLES_sum") / kib, g("TCC_TAG_STALL_sum") / kib,
+            g("TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum") / kib, g("TCC_EA0_WRREQ_DRAM_CREDIT_STALL_sum") / kib,
+            g("TCP_UTCL1_TRANSLATION_MISS_sum") / kib))
+    out = os.path.join(ROOT, "profiles", "hot_path_step_n2e28_memory_counters.txt")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 VALU64 = "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 " \

@@ -7,14 +7,15 @@
 // by the first threads of block 0; misaligned arrays take a scalar kernel.
 #include "tf_internal.hpp"
 
-// Vectors in flight per thread, tuned on MI355X at n = 2^28: one 16-byte
-// vector per operand per thread in both types (binary32 with four: 1.3-2.8 %
-// slower, the texture addresser stalled by the L1 twenty times as often).
+// Vectors in flight per thread, tuned on MI355X at n = 2^28: binary64
+// kernels run best with one 16-byte vector per operand per thread, binary32
+// binary operations with four (the square root, with half the streams,
+// with one).
 #ifndef TF_EW_UNROLL_F64
 #define TF_EW_UNROLL_F64 1
 #endif
 #ifndef TF_EW_UNROLL_F32
-#define TF_EW_UNROLL_F32 1
+#define TF_EW_UNROLL_F32 4
 #endif
 #ifndef TF_EW_UNROLL_F32_UNARY
 #define TF_EW_UNROLL_F32_UNARY 1
