@@ -36,6 +36,15 @@
 
 namespace tf {
 
+// Waves per worker block.  A unit is processed by the whole block, and the
+// tree of a reduction unit does not depend on how many waves share it.
+#ifndef TF_SERVE_WAVES
+#define TF_SERVE_WAVES 8
+#endif
+static_assert(TF_SERVE_WAVES == 4 || TF_SERVE_WAVES == 8 || TF_SERVE_WAVES == 16, "4, 8 or 16 waves per worker");
+constexpr int kServeWaves = TF_SERVE_WAVES;
+constexpr int kServeBlock = 64 * kServeWaves;
+
 // ---------------------------------------------------------------------------
 // counter-based input generator (same recipe as the host test generator)
 // ---------------------------------------------------------------------------
@@ -129,10 +138,11 @@ __device__ void gen_unit(const tfs_desc &d, int unit) {
     const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
     if (end - base == TFS_CLAIM) {
 #pragma unroll 4
-        for (int k = 0; k < TFS_CLAIM / kBlock; ++k)
-            gen_elem<T>(x0, x1, y0, y1, s, base + k * kBlock + threadIdx.x, horner, ill, a0);
+        for (int k = 0; k < TFS_CLAIM / kServeBlock; ++k)
+            gen_elem<T>(x0, x1, y0, y1, s, base + k * kServeBlock + threadIdx.x, horner, ill, a0);
     } else {
-        for (int64_t i = base + threadIdx.x; i < end; i += kBlock) gen_elem<T>(x0, x1, y0, y1, s, i, horner, ill, a0);
+        for (int64_t i = base + threadIdx.x; i < end; i += kServeBlock)
+            gen_elem<T>(x0, x1, y0, y1, s, i, horner, ill, a0);
     }
 }
 
@@ -246,8 +256,8 @@ __device__ void claim_reduce(const tfs_desc &d, int claim) {
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
     const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1) & 15u) == 0;
     const int64_t tiles = (d.n + kTile - 1) / kTile;
-    const Pair<T> r = block_subtree<T, LEAF, 4, false, TF_SERVE_RED_PIPE>(claim, d.tiles_per_claim, d.n, tiles,
-                                                                          aligned, x0, x1, y0, y1);
+    const Pair<T> r = block_subtree<T, LEAF, kServeWaves, false, TF_SERVE_RED_PIPE>(
+        claim, d.tiles_per_claim, d.n, tiles, aligned, x0, x1, y0, y1);
     if (threadIdx.x == 0) ((Pair<T> *)d.part)[claim] = r;
 }
 
@@ -260,11 +270,11 @@ __device__ __forceinline__ uint64_t bits_of(T v) {
 // Block-wide reduction of a vector unit's summary (max is exact and the
 // sums are integers, so the order does not matter); result in thread 0.
 __device__ tfs_vsum block_summary(tfs_vsum v) {
-    __shared__ tfs_vsum s[kBlock];
+    __shared__ tfs_vsum s[kServeBlock];
     const int t = threadIdx.x;
     s[t] = v;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = kServeBlock / 2; w > 0; w >>= 1) {
         if (t < w) {
             s[t].max0 = fmax(s[t].max0, s[t + w].max0);
             s[t].max1 = fmax(s[t].max1, s[t + w].max1);
@@ -320,7 +330,7 @@ template <typename T, int OP, bool XT, bool YT>
 __device__ void claim_vector(const tfs_desc &d, int claim) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
-    constexpr int NV = TFS_CLAIM / kBlock / W;  // vectors per thread
+    constexpr int NV = TFS_CLAIM / kServeBlock / W;  // vectors per thread
     constexpr int U = NV < TF_SERVE_VEC_GROUP ? NV : TF_SERVE_VEC_GROUP;
     constexpr bool HAS_Y = OP == TFS_OP_AXPY;
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
@@ -338,7 +348,7 @@ __device__ void claim_vector(const tfs_desc &d, int claim) {
             V p0[U], p1[U], q0[U], q1[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t i = vb + (int64_t)(j0 + u) * kBlock + t;
+                const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + t;
                 p0[u] = vload(x0, i);
                 if constexpr (XT) p1[u] = vload(x1, i);
                 if constexpr (HAS_Y) q0[u] = vload(y0, i);
@@ -383,13 +393,13 @@ __device__ void claim_vector(const tfs_desc &d, int claim) {
                     r1[k] = z[u][k].lo;
                     account(acc, z[u][k].hi, z[u][k].lo, d.thr);
                 }
-                const int64_t i = vb + (int64_t)(j0 + u) * kBlock + t;
+                const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + t;
                 vstore(z0, i, r0);
                 vstore(z1, i, r1);
             }
         }
     } else {
-        for (int64_t i = base + t; i < end; i += kBlock) {
+        for (int64_t i = base + t; i < end; i += kServeBlock) {
             const Pair<T> z = vector_elem<T, OP, XT, YT>(d, a0, a1, x0[i], XT ? x1[i] : T(0),
                                                         HAS_Y ? y0[i] : T(0), (HAS_Y && YT) ? y1[i] : T(0));
             z0[i] = z.hi;
@@ -435,7 +445,7 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
     if (d.op == TFS_OP_SUM || d.op == TFS_OP_DOT) {
         // four partials per lane in flight: the serving kernel's register budget is set
         // by its largest path, and two waves per SIMD must fit
-        const Pair<T> r = block_join<T, false, 4, 4>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
+        const Pair<T> r = block_join<T, false, kServeWaves, 4>(0, d.nclaims, d.padded, (const Pair<T> *)d.part);
         const double z0 = (double)r.hi, z1 = (double)r.lo;
         out.z0 = z0;
         out.z1 = z1;
@@ -445,7 +455,7 @@ __device__ void finalize(const tfs_desc &d, DevSlot *S, uint64_t *ctl, tfs_done 
     } else {
         tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
         const tfs_vsum *p = (const tfs_vsum *)d.part;
-        for (int k = threadIdx.x; k < d.nclaims; k += kBlock) {
+        for (int k = threadIdx.x; k < d.nclaims; k += kServeBlock) {
             acc.max0 = fmax(acc.max0, p[k].max0);
             acc.max1 = fmax(acc.max1, p[k].max1);
             acc.n_flagged += p[k].n_flagged;
@@ -581,7 +591,7 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
         if (fresh) {  // the block's copy of the descriptor is for another job
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const uint64_t *src = (const uint64_t *)&S->d;
-            for (unsigned k = t; k < sizeof(tfs_desc) / 8; k += kBlock) s_desc[k] = src[k];
+            for (unsigned k = t; k < sizeof(tfs_desc) / 8; k += kServeBlock) s_desc[k] = src[k];
             if (t == 0) {
                 s_have_slot = slot;
                 s_have_gen = gen;
@@ -635,9 +645,10 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
     }
 }
 
-// Every worker block must be resident: with k worker blocks of 256 threads
-// per CU each SIMD holds k waves, so the registers are capped for k.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_SERVE_WORKERS_PER_CU)))
+// Every worker block must be resident: with k worker blocks of w waves per
+// CU each SIMD holds k w / 4 waves, so the registers are capped for that.
+__global__ __launch_bounds__(kServeBlock)
+__attribute__((amdgpu_waves_per_eu(TF_SERVE_WORKERS_PER_CU * TF_SERVE_WAVES / 4)))
 void serve_kernel(tfs_shared *sh, DevState *st, uint64_t idle_ticks) {
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) dispatcher(sh, st, idle_ticks);
@@ -698,7 +709,7 @@ class HipDevice : public tfs::DeviceOps {
         // shared with other streams of the process, whose work waits until
         // it exits; the host relaunches it with the next job.
         const uint64_t idle = (uint64_t)(0.02 * tick_hz_);
-        return tf_launch(serve_kernel, dim3(1 + workers_), dim3(kBlock), 0, work_, shared_, state_, idle) == hipSuccess
+        return tf_launch(serve_kernel, dim3(1 + workers_), dim3(kServeBlock), 0, work_, shared_, state_, idle) == hipSuccess
                    ? TF_OK
                    : TF_EDEVICE;
     }
