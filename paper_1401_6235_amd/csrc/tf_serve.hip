@@ -327,7 +327,7 @@ __device__ __forceinline__ Pair<T> vector_elem(const tfs_desc &d, T a0, T a1, T 
 // vectors per operand in flight, consecutive threads on consecutive vectors; a short
 // or misaligned unit takes a scalar loop.
 template <typename T, int OP, bool XT, bool YT>
-__device__ void claim_vector(const tfs_desc &d, int claim) {
+__device__ __forceinline__ void claim_vector(const tfs_desc &d, int claim, tfs_vsum &acc) {
     using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     constexpr int NV = TFS_CLAIM / kServeBlock / W;  // vectors per thread
@@ -340,7 +340,6 @@ __device__ void claim_vector(const tfs_desc &d, int claim) {
     const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
     const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1 | d.z0 | d.z1) & 15u) == 0;
     const T a0 = (T)d.a0, a1 = (T)d.a1;
-    tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
     if (aligned && end == base + TFS_CLAIM) {
         const int64_t vb = base / W;
 #pragma unroll
@@ -407,33 +406,53 @@ __device__ void claim_vector(const tfs_desc &d, int claim) {
             account(acc, z.hi, z.lo, d.thr);
         }
     }
-    const tfs_vsum r = block_summary(acc);
-    if (t == 0) ((tfs_vsum *)d.part)[claim] = r;
 }
 
+// The vector units [claim, claim + count) of a job with one block summary
+// for the batch, written as the first unit's partial; the batch's other
+// partials are zero.  A summary holds maxima of magnitudes and sums, for
+// which zero is neutral, so the job's totals do not depend on the batching.
+template <typename T, int OP, bool XT, bool YT>
+__device__ void vector_units(const tfs_desc &d, int claim, int count) {
+    tfs_vsum acc = {0.0, 0.0, 0, 0, 0, 0};
+    for (int c = claim; c < claim + count; ++c) claim_vector<T, OP, XT, YT>(d, c, acc);
+    const tfs_vsum r = block_summary(acc);
+    if (threadIdx.x == 0) {
+        tfs_vsum *part = (tfs_vsum *)d.part;
+        part[claim] = r;
+        for (int c = claim + 1; c < claim + count; ++c) part[c] = tfs_vsum{0.0, 0.0, 0, 0, 0, 0};
+    }
+}
+
+// The compute units [claim, claim + count) of a job: reduction units one by
+// one (one partial each), vector units as one batch.
 template <typename T>
-__device__ void run_claim(const tfs_desc &d, int claim) {
+__device__ void run_units(const tfs_desc &d, int claim, int count) {
     const bool xt = d.x1 != 0, yt = d.y1 != 0;
     switch (d.op) {
     case TFS_OP_SUM:
-        if (xt) claim_reduce<T, LEAF_SUM_T>(d, claim);
-        else claim_reduce<T, LEAF_SUM_D>(d, claim);
+        for (int c = claim; c < claim + count; ++c) {
+            if (xt) claim_reduce<T, LEAF_SUM_T>(d, c);
+            else claim_reduce<T, LEAF_SUM_D>(d, c);
+        }
         break;
     case TFS_OP_DOT:
-        if (xt && yt) claim_reduce<T, LEAF_DOT_TT>(d, claim);
-        else if (xt) claim_reduce<T, LEAF_DOT_TD>(d, claim);
-        else if (yt) claim_reduce<T, LEAF_DOT_DT>(d, claim);
-        else claim_reduce<T, LEAF_DOT_DD>(d, claim);
+        for (int c = claim; c < claim + count; ++c) {
+            if (xt && yt) claim_reduce<T, LEAF_DOT_TT>(d, c);
+            else if (xt) claim_reduce<T, LEAF_DOT_TD>(d, c);
+            else if (yt) claim_reduce<T, LEAF_DOT_DT>(d, c);
+            else claim_reduce<T, LEAF_DOT_DD>(d, c);
+        }
         break;
     case TFS_OP_AXPY:
-        if (xt && yt) claim_vector<T, TFS_OP_AXPY, true, true>(d, claim);
-        else if (xt) claim_vector<T, TFS_OP_AXPY, true, false>(d, claim);
-        else if (yt) claim_vector<T, TFS_OP_AXPY, false, true>(d, claim);
-        else claim_vector<T, TFS_OP_AXPY, false, false>(d, claim);
+        if (xt && yt) vector_units<T, TFS_OP_AXPY, true, true>(d, claim, count);
+        else if (xt) vector_units<T, TFS_OP_AXPY, true, false>(d, claim, count);
+        else if (yt) vector_units<T, TFS_OP_AXPY, false, true>(d, claim, count);
+        else vector_units<T, TFS_OP_AXPY, false, false>(d, claim, count);
         break;
     default:
-        if (xt) claim_vector<T, TFS_OP_HORNER, true, false>(d, claim);
-        else claim_vector<T, TFS_OP_HORNER, false, false>(d, claim);
+        if (xt) vector_units<T, TFS_OP_HORNER, true, false>(d, claim, count);
+        else vector_units<T, TFS_OP_HORNER, false, false>(d, claim, count);
     }
 }
 
@@ -602,14 +621,14 @@ __device__ void worker(tfs_shared *sh, DevState *st) {
         const tfs_desc &d = *(const tfs_desc *)s_desc;
         const bool gen_phase = phase == TFS_PHASE_GEN;
         if (claim == 0 && t == 0 && (gen_phase || d.ngen == 0)) S->t_start = wall_clock64();
-        for (int c = claim; c < claim + count; ++c) {
-            if (gen_phase) {
+        if (gen_phase) {
+            for (int c = claim; c < claim + count; ++c) {
                 if (d.dtype == TF_F64) gen_unit<double>(d, c);
                 else gen_unit<float>(d, c);
-            } else {
-                if (d.dtype == TF_F64) run_claim<double>(d, c);
-                else run_claim<float>(d, c);
             }
+        } else if (count > 0) {
+            if (d.dtype == TF_F64) run_units<double>(d, claim, count);
+            else run_units<float>(d, claim, count);
         }
         __syncthreads();
         if (t == 0) {
