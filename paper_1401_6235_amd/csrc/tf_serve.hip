@@ -323,82 +323,107 @@ __device__ __forceinline__ Pair<T> vector_elem(const tfs_desc &d, T a0, T a1, T 
 }
 
 
-// TFS_CLAIM elements: 16 per thread as 16-byte vectors, TF_SERVE_VEC_GROUP
-// vectors per operand in flight, consecutive threads on consecutive vectors; a short
-// or misaligned unit takes a scalar loop.
+// One round of a vector unit: U 16-byte vectors per operand and thread,
+// consecutive threads on consecutive vectors.
+template <typename T, int U>
+struct VecRound {
+    using V = typename Vec<T>::type;
+    V p0[U], p1[U], q0[U], q1[U];
+};
+
+// Loads the round of U vectors per operand starting at vector j0 of the
+// unit whose first vector is vb.
+template <typename T, int OP, bool XT, bool YT, int U>
+__device__ __forceinline__ void round_load(const tfs_desc &d, VecRound<T, U> &R, int64_t vb, int j0) {
+    constexpr bool HAS_Y = OP == TFS_OP_AXPY;
+    const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + threadIdx.x;
+        R.p0[u] = vload(x0, i);
+        if constexpr (XT) R.p1[u] = vload(x1, i);
+        if constexpr (HAS_Y) R.q0[u] = vload(y0, i);
+        if constexpr (HAS_Y && YT) R.q1[u] = vload(y1, i);
+    }
+}
+
+// Computes and stores a loaded round, adding its elements to the summary.
+template <typename T, int OP, bool XT, bool YT, int U>
+__device__ __forceinline__ void round_run(const tfs_desc &d, const VecRound<T, U> &R, int64_t vb, int j0,
+                                          tfs_vsum &acc) {
+    using V = typename Vec<T>::type;
+    constexpr int W = Vec<T>::N;
+    constexpr bool HAS_Y = OP == TFS_OP_AXPY;
+    T *z0 = (T *)d.z0, *z1 = (T *)d.z1;
+    Pair<T> z[U][W];
+    if constexpr (OP == TFS_OP_HORNER) {
+        // the U * W elements' Horner steps interleaved (degree loop outside),
+        // each element's operations unchanged: a wave has that many
+        // independent chains to issue
+        const T cd = (T)d.c[d.degree];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < W; ++k) z[u][k] = Pair<T>{cd, T(0)};
+        for (int j = d.degree - 1; j >= 0; --j) {
+            const T cj = (T)d.c[j];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const Pair<T> m = XT ? mul_tt(z[u][k].hi, z[u][k].lo, R.p0[u][k], R.p1[u][k])
+                                         : mul_td(z[u][k].hi, z[u][k].lo, R.p0[u][k]);
+                    z[u][k] = add_td(m.hi, m.lo, cj);
+                }
+        }
+    } else {
+        const T a0 = (T)d.a0, a1 = (T)d.a1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                z[u][k] = vector_elem<T, OP, XT, YT>(d, a0, a1, R.p0[u][k], XT ? R.p1[u][k] : T(0),
+                                                     HAS_Y ? R.q0[u][k] : T(0), (HAS_Y && YT) ? R.q1[u][k] : T(0));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        V r0, r1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            r0[k] = z[u][k].hi;
+            r1[k] = z[u][k].lo;
+            account(acc, z[u][k].hi, z[u][k].lo, d.thr);
+        }
+        const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + threadIdx.x;
+        vstore(z0, i, r0);
+        vstore(z1, i, r1);
+    }
+}
+
+// One unit of TFS_CLAIM elements, added to the summary: 16-byte vectors,
+// TF_SERVE_VEC_GROUP per operand in flight, consecutive threads on
+// consecutive vectors; a short or misaligned unit takes a scalar loop.
 template <typename T, int OP, bool XT, bool YT>
 __device__ __forceinline__ void claim_vector(const tfs_desc &d, int claim, tfs_vsum &acc) {
-    using V = typename Vec<T>::type;
     constexpr int W = Vec<T>::N;
     constexpr int NV = TFS_CLAIM / kServeBlock / W;  // vectors per thread
     constexpr int U = NV < TF_SERVE_VEC_GROUP ? NV : TF_SERVE_VEC_GROUP;
     constexpr bool HAS_Y = OP == TFS_OP_AXPY;
     const T *x0 = (const T *)d.x0, *x1 = (const T *)d.x1, *y0 = (const T *)d.y0, *y1 = (const T *)d.y1;
     T *z0 = (T *)d.z0, *z1 = (T *)d.z1;
-    const int t = threadIdx.x;
     const int64_t base = (int64_t)claim * TFS_CLAIM;
     const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
     const bool aligned = ((d.x0 | d.x1 | d.y0 | d.y1 | d.z0 | d.z1) & 15u) == 0;
-    const T a0 = (T)d.a0, a1 = (T)d.a1;
     if (aligned && end == base + TFS_CLAIM) {
-        const int64_t vb = base / W;
 #pragma unroll
         for (int j0 = 0; j0 < NV; j0 += U) {
-            V p0[U], p1[U], q0[U], q1[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + t;
-                p0[u] = vload(x0, i);
-                if constexpr (XT) p1[u] = vload(x1, i);
-                if constexpr (HAS_Y) q0[u] = vload(y0, i);
-                if constexpr (HAS_Y && YT) q1[u] = vload(y1, i);
-            }
-            Pair<T> z[U][W];
-            if constexpr (OP == TFS_OP_HORNER) {
-                // the U * W elements' Horner steps interleaved (degree loop
-                // outside), each element's operations unchanged: one wave per
-                // SIMD then has independent chains to issue
-                const T cd = (T)d.c[d.degree];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < W; ++k) z[u][k] = Pair<T>{cd, T(0)};
-                for (int j = d.degree - 1; j >= 0; --j) {
-                    const T cj = (T)d.c[j];
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int k = 0; k < W; ++k) {
-                            const Pair<T> m = XT ? mul_tt(z[u][k].hi, z[u][k].lo, p0[u][k], p1[u][k])
-                                                 : mul_td(z[u][k].hi, z[u][k].lo, p0[u][k]);
-                            z[u][k] = add_td(m.hi, m.lo, cj);
-                        }
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < W; ++k)
-                        z[u][k] = vector_elem<T, OP, XT, YT>(d, a0, a1, p0[u][k], XT ? p1[u][k] : T(0),
-                                                             HAS_Y ? q0[u][k] : T(0),
-                                                             (HAS_Y && YT) ? q1[u][k] : T(0));
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                V r0, r1;
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    r0[k] = z[u][k].hi;
-                    r1[k] = z[u][k].lo;
-                    account(acc, z[u][k].hi, z[u][k].lo, d.thr);
-                }
-                const int64_t i = vb + (int64_t)(j0 + u) * kServeBlock + t;
-                vstore(z0, i, r0);
-                vstore(z1, i, r1);
-            }
+            VecRound<T, U> R;
+            round_load<T, OP, XT, YT, U>(d, R, base / W, j0);
+            round_run<T, OP, XT, YT, U>(d, R, base / W, j0, acc);
         }
     } else {
-        for (int64_t i = base + t; i < end; i += kServeBlock) {
+        const T a0 = (T)d.a0, a1 = (T)d.a1;
+        for (int64_t i = base + threadIdx.x; i < end; i += kServeBlock) {
             const Pair<T> z = vector_elem<T, OP, XT, YT>(d, a0, a1, x0[i], XT ? x1[i] : T(0),
                                                         HAS_Y ? y0[i] : T(0), (HAS_Y && YT) ? y1[i] : T(0));
             z0[i] = z.hi;
