@@ -391,15 +391,15 @@ __device__ __forceinline__ Pair<T> butterfly_m(Pair<T> v, int lane, int m) {
 
 // Join of the wave results of a block (`waves` a power of two, at most
 // MAXW): adjacent pairs, level by level, the same tree as the leaves'.
-template <typename T, bool PLAIN, int MAXW = 4>
-__device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
-    __shared__ Pair<T> wres[MAXW];
+// Wave w's result is exchanged through LDS at wres[w * stride].
+template <typename T, bool PLAIN, int MAXW>
+__device__ __forceinline__ Pair<T> join_waves_via(Pair<T> mine, int waves, Pair<T> *wres, int stride) {
     const int wave = threadIdx.x >> 6;
-    if (wave < waves && (threadIdx.x & 63) == 0) wres[wave] = mine;
+    if (wave < waves && (threadIdx.x & 63) == 0) wres[wave * stride] = mine;
     __syncthreads();
     Pair<T> v[MAXW];
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k) v[k] = k < waves ? wres[k] : Pair<T>{T(0), T(0)};
+    for (int k = 0; k < MAXW; ++k) v[k] = k < waves ? wres[k * stride] : Pair<T>{T(0), T(0)};
 #pragma unroll
     for (int w = MAXW; w > 1; w >>= 1) {
         if (w <= waves) {
@@ -409,6 +409,12 @@ __device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
     }
     __syncthreads();
     return v[0];
+}
+
+template <typename T, bool PLAIN, int MAXW = 4>
+__device__ __forceinline__ Pair<T> join_waves(Pair<T> mine, int waves) {
+    __shared__ Pair<T> wres[MAXW];
+    return join_waves_via<T, PLAIN, MAXW>(mine, waves, wres, 1);
 }
 
 // Value of the aligned subtree of `per_block` tiles (a power of two, at most
@@ -433,6 +439,18 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
     const int per_wave = per_block >= WAVES ? per_block / WAVES : 1;
     const int waves = per_block / per_wave;
     Pair<T> mine{T(0), T(0)};
+    // Where a kernel has the tile-pair LDS region, each wave hands its result
+    // to the join through the start of its own region (which it no longer
+    // needs): no separate LDS array, so 8-wave blocks take exactly 40 KiB and
+    // four fit in a compute unit's 160 KiB.
+    constexpr bool PAIR_LDS = TF_RED_PAIRS && LeafTraits<LEAF>::arrays <= TF_RED_PAIR_ARRAYS;
+    auto join = [&](Pair<T> m, int w) {
+        if constexpr (PAIR_LDS)
+            return join_waves_via<T, PLAIN, WAVES>(m, w, reinterpret_cast<Pair<T> *>(pair_lds_base<WAVES>()),
+                                                   (int)(PairLayout<T>::SLOTS * 16 / sizeof(Pair<T>)));
+        else
+            return join_waves<T, PLAIN, WAVES>(m, w);
+    };
 #if TF_RED_PAIRS
     // Tile pairs pay off where the tree dominates the per-leaf work: leaves
     // read from one or two arrays (sums, dot of plain vectors).  Leaves with
@@ -456,7 +474,7 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
                 }
             }
             mine = butterfly_m<T, PLAIN>(mine, lane, PL::TILES);
-            return join_waves<T, PLAIN, WAVES>(mine, waves);
+            return join(mine, waves);
         }
         if constexpr (!PIPE) {
             for (int p = 0; PL::TILES * p < per_wave; ++p) {
@@ -473,7 +491,7 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
                 }
             }
             mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
-            return join_waves<T, PLAIN, WAVES>(mine, waves);
+            return join(mine, waves);
         }
         // the next group's loads are in flight while the current one is reduced
         PairData<T> cur, nxt;
@@ -493,7 +511,7 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
             cur = nxt;
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
-        return join_waves<T, PLAIN, WAVES>(mine, waves);
+        return join(mine, waves);
     }
 #endif
     if (!PIPE && wave < waves) {
@@ -526,7 +544,7 @@ __device__ __forceinline__ Pair<T> block_subtree(int64_t b, int per_block, int64
         }
         mine = butterfly_m<T, PLAIN>(mine, lane, per_wave);
     }
-    return join_waves<T, PLAIN, WAVES>(mine, waves);
+    return join(mine, waves);
 }
 
 // Join of the aligned group of `span` partials (a power of two, at most
