@@ -539,6 +539,8 @@ def alg_bytes(key: str):
     b = base[6:] if plain else base
     if b == "vmem":
         return 3 * es * N_STREAM
+    if plain and base in PLAIN_WORDS:
+        return PLAIN_WORDS[base] * es * (N_REDUCE if b in ("sum", "dot") else N_STREAM)
     if b in KERNELS:
         n = N_REDUCE if b in ("sum", "dot") else N_STREAM
         return KERNELS[b][0] * es * n
@@ -580,7 +582,7 @@ def _bench_dispatches(rows, name_col, grid_col):
     return out
 
 
-def summarize_profiles(prof_dir: str, command: str):
+def summarize_profiles(prof_dir: str, command: str, out_dir: str = None):
     """Write profiles/<group>_kernel_trace.txt, <group>_counters.txt and
     profiles/traffic.json from rocprofv3 runs of this benchmark: kernel
     statistics (--kernel-trace --stats) in prof_dir/trace, FETCH_SIZE and
@@ -589,7 +591,7 @@ def summarize_profiles(prof_dir: str, command: str):
     makes them equal the known bytes of the copy kernel (vmem)."""
     import csv
     import glob
-    out_dir = os.path.join(ROOT, "profiles")
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     trace = glob.glob(os.path.join(prof_dir, "trace", "*kernel_trace.csv"))[0]
     disp = _bench_dispatches(csv.DictReader(open(trace)), "Kernel_Name", "Grid_Size_X")
@@ -648,8 +650,8 @@ def summarize_profiles(prof_dir: str, command: str):
         print("\n".join(lines))
     json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
     if os.path.isdir(os.path.join(prof_dir, "valu64")) and os.path.isdir(os.path.join(prof_dir, "valu32")):
-        summarize_valu(prof_dir, command, rows)
-    summarize_memory(prof_dir, command)
+        summarize_valu(prof_dir, command, rows, out_dir)
+    summarize_memory(prof_dir, command, out_dir)
 
 
 # Memory-pipeline counter sets (one rocprofv3 --pmc run each, directories
@@ -665,7 +667,7 @@ MEM_SETS = [
 ]
 
 
-def summarize_memory(prof_dir: str, command: str):
+def summarize_memory(prof_dir: str, command: str, out_dir: str = None):
     """profiles/hot_path_step_n2e28_memory_counters.txt from the MEM_SETS
     runs: per streaming kernel of the step, requests to HBM, the L1's
     average read / write latency to the L2, stalls of the texture addresser
@@ -704,7 +706,7 @@ def summarize_memory(prof_dir: str, command: str):
             g("TA_ADDR_STALLED_BY_TC_CYCLES_sum") / kib, g("TCC_TAG_STALL_sum") / kib,
             g("TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum") / kib, g("TCC_EA0_WRREQ_DRAM_CREDIT_STALL_sum") / kib,
             g("TCP_UTCL1_TRANSLATION_MISS_sum") / kib))
-    out = os.path.join(ROOT, "profiles", "hot_path_step_n2e28_memory_counters.txt")
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), "hot_path_step_n2e28_memory_counters.txt")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -715,7 +717,7 @@ VALU32 = "SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 SQ_I
          "SQ_THREAD_CYCLES_VALU GRBM_GUI_ACTIVE"
 
 
-def summarize_valu(prof_dir: str, command: str, trace_rows):
+def summarize_valu(prof_dir: str, command: str, trace_rows, out_dir: str = None):
     """profiles/<group>_valu.txt from two --pmc runs (VALU64, VALU32
     counters) of the benchmark: executed FP64 / FP32 operations per launch
     (each ADD / MUL / TRANS wave instruction is 64 operations, each FMA 128)
@@ -770,7 +772,8 @@ def summarize_valu(prof_dir: str, command: str, trace_rows):
             lines.append("%-28s %10.1f %12.2f %8.4f %12.2f %8.4f %9.3f %6.2f" % (
                 k, t * 1e6, f64 / t / 1e12, f64 / t / 1e12 / FP_PEAK_TFLOPS["f64"], f32 / t / 1e12,
                 f32 / t / 1e12 / FP_PEAK_TFLOPS["f32"], ipc, ghz))
-        open(os.path.join(ROOT, "profiles", fname + "_valu.txt"), "w").write("\n".join(lines) + "\n")
+        open(os.path.join(out_dir or os.path.join(ROOT, "profiles"), fname + "_valu.txt"), "w").write(
+            "\n".join(lines) + "\n")
         print("\n".join(lines))
 
 

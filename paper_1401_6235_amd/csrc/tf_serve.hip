@@ -323,6 +323,8 @@ __device__ __forceinline__ Pair<T> vector_elem(const tfs_desc &d, T a0, T a1, T 
 }
 
 
+static_assert(TF_MAX_DEGREE < 64, "a wave's lanes hold the Horner coefficients");
+
 // One round of a vector unit: U 16-byte vectors per operand and thread,
 // consecutive threads on consecutive vectors.
 template <typename T, int U>
@@ -359,14 +361,18 @@ __device__ __forceinline__ void round_run(const tfs_desc &d, const VecRound<T, U
     if constexpr (OP == TFS_OP_HORNER) {
         // the U * W elements' Horner steps interleaved (degree loop outside),
         // each element's operations unchanged: a wave has that many
-        // independent chains to issue
-        const T cd = (T)d.c[d.degree];
+        // independent chains to issue.  Lane k holds coefficient k (degree
+        // <= 32 < 64), and each step takes its coefficient with a readlane:
+        // no LDS read and wait inside the degree loop.
+        const int lane = threadIdx.x & 63;
+        const T cl = (T)d.c[lane <= d.degree ? lane : 0];
+        const T cd = readlane_t(cl, d.degree);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int k = 0; k < W; ++k) z[u][k] = Pair<T>{cd, T(0)};
         for (int j = d.degree - 1; j >= 0; --j) {
-            const T cj = (T)d.c[j];
+            const T cj = readlane_t(cl, j);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
