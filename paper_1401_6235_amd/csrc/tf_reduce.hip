@@ -84,14 +84,19 @@ static int64_t pow2_ceil(int64_t v) {
     return p;
 }
 
-// First-pass geometry when none is configured, the fastest whole call
-// (first pass plus the joins of its partials) of a sweep on MI355X at
-// n = 2^26 over 8-128 tiles and 4, 8 or 16 waves per block:
-//   binary32, leaves from one or two arrays   32 tiles, 8 waves (one group
-//                                             of tile pairs per wave)
-//   binary32, leaves from three or four       32 tiles, 4 waves
-//   binary64, leaves from one or two arrays   64 tiles, 8 waves
-//   binary64, leaves from three or four       16 tiles, 4 waves
+// First-pass geometry when none is configured: per element size and leaf
+// kind, the fastest whole call (first pass plus the joins of its partials)
+// of sweeps on MI355X at n = 2^26 over 8-256 tiles and 4, 8 or 16 waves per
+// block, confirmed by alternating per-call runs after a streaming kernel
+// (as in the benchmark step):
+//   binary32 twofold sum                      32 tiles,  8 waves
+//   binary32 dotted sum, plain sum            128 tiles, 16 waves
+//   binary32 dot of dotted vectors, plain dot 64 tiles,  16 waves
+//   binary32, leaves from three or four       32 tiles,  4 waves
+//   binary64 twofold and dotted sum, dot of   64 tiles,  8 waves
+//   dotted vectors
+//   binary64 plain sum and dot                64 tiles,  16 waves
+//   binary64, leaves from three or four       16 tiles,  4 waves
 static int leaf_arrays(int leaf) {
     switch (leaf) {
     case LEAF_SUM_D: case LEAF_PSUM: return 1;
@@ -101,14 +106,21 @@ static int leaf_arrays(int leaf) {
     }
 }
 
-static int64_t auto_tiles_per_block(int elem_size, int leaf) {
-    if (elem_size == 4) return 32;
-    return leaf_arrays(leaf) <= 2 ? 64 : 16;
-}
+struct AutoShape {
+    int64_t tiles;
+    int waves;
+};
 
-static int auto_waves(int elem_size, int leaf) {
-    (void)elem_size;
-    return leaf_arrays(leaf) <= 2 ? 8 : 4;
+static AutoShape auto_shape(int elem_size, int leaf) {
+    if (leaf_arrays(leaf) > 2) return elem_size == 4 ? AutoShape{32, 4} : AutoShape{16, 4};
+    if (elem_size == 4) {
+        switch (leaf) {
+        case LEAF_SUM_T: return {32, 8};
+        case LEAF_SUM_D: case LEAF_PSUM: return {128, 16};
+        default: return {64, 16};  // dot of dotted vectors, plain dot
+        }
+    }
+    return leaf == LEAF_PSUM || leaf == LEAF_PDOT ? AutoShape{64, 16} : AutoShape{64, 8};
 }
 
 RedShape reduce_shape(int64_t n, int64_t per_block) {
@@ -125,14 +137,14 @@ RedShape reduce_shape(int64_t n, int64_t per_block) {
 
 int64_t tiles_per_block(int elem_size, int leaf) {
     const int64_t c = config().red_tiles_per_block;
-    return c > 0 ? c : auto_tiles_per_block(elem_size, leaf);
+    return c > 0 ? c : auto_shape(elem_size, leaf).tiles;
 }
 
 // Waves per first-pass block: the configured 4, 8 or 16, else the tuned
 // value; never more waves than tiles.
 static int reduce_waves(int elem_size, int leaf, int64_t per_block) {
     int64_t w = config().red_waves;
-    if (w == 0) w = auto_waves(elem_size, leaf);
+    if (w == 0) w = auto_shape(elem_size, leaf).waves;
     while (w > 4 && w > per_block) w /= 2;
     return (int)w;
 }
