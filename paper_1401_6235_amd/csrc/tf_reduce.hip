@@ -93,9 +93,7 @@ static int64_t pow2_ceil(int64_t v) {
 //   binary32 dotted sum, plain sum            128 tiles, 16 waves
 //   binary32 dot of dotted vectors, plain dot 64 tiles,  16 waves
 //   binary32, leaves from three or four       32 tiles,  4 waves
-//   binary64 twofold and dotted sum, dot of   64 tiles,  8 waves
-//   dotted vectors
-//   binary64 plain sum and dot                64 tiles,  16 waves
+//   binary64, leaves from one or two arrays   64 tiles,  16 waves
 //   binary64, leaves from three or four       16 tiles,  4 waves
 static int leaf_arrays(int leaf) {
     switch (leaf) {
@@ -120,7 +118,7 @@ static AutoShape auto_shape(int elem_size, int leaf) {
         default: return {64, 16};  // dot of dotted vectors, plain dot
         }
     }
-    return leaf == LEAF_PSUM || leaf == LEAF_PDOT ? AutoShape{64, 16} : AutoShape{64, 8};
+    return {64, 16};
 }
 
 RedShape reduce_shape(int64_t n, int64_t per_block) {

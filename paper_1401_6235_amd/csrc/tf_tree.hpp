@@ -391,24 +391,20 @@ __device__ __forceinline__ Pair<T> butterfly_m(Pair<T> v, int lane, int m) {
 
 // Join of the wave results of a block (`waves` a power of two, at most
 // MAXW): adjacent pairs, level by level, the same tree as the leaves'.
-// Wave w's result is exchanged through LDS at wres[w * stride].
+// Wave w's result is exchanged through LDS at wres[w * stride]; lane k of
+// every wave then takes wave k's result and a butterfly over the first
+// `waves` lanes forms the tree (one pair per lane in registers, whatever
+// MAXW), whose root lane 0 holds and hands to the whole wave.
 template <typename T, bool PLAIN, int MAXW>
 __device__ __forceinline__ Pair<T> join_waves_via(Pair<T> mine, int waves, Pair<T> *wres, int stride) {
-    const int wave = threadIdx.x >> 6;
-    if (wave < waves && (threadIdx.x & 63) == 0) wres[wave * stride] = mine;
+    static_assert(MAXW <= 64, "one wave result per lane");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave < waves && lane == 0) wres[wave * stride] = mine;
     __syncthreads();
-    Pair<T> v[MAXW];
-#pragma unroll
-    for (int k = 0; k < MAXW; ++k) v[k] = k < waves ? wres[k * stride] : Pair<T>{T(0), T(0)};
-#pragma unroll
-    for (int w = MAXW; w > 1; w >>= 1) {
-        if (w <= waves) {
-#pragma unroll
-            for (int k = 0; k < w / 2; ++k) v[k] = node<T, PLAIN>(v[2 * k], v[2 * k + 1]);
-        }
-    }
+    Pair<T> v = lane < waves ? wres[lane * stride] : Pair<T>{T(0), T(0)};
+    v = butterfly_m<T, PLAIN>(v, lane, waves);
     __syncthreads();
-    return v[0];
+    return Pair<T>{readlane_t(v.hi, 0), readlane_t(v.lo, 0)};
 }
 
 template <typename T, bool PLAIN, int MAXW = 4>
