@@ -89,9 +89,9 @@ static int64_t pow2_ceil(int64_t v) {
 // of sweeps on MI355X at n = 2^26 over 8-256 tiles and 4, 8 or 16 waves per
 // block, confirmed by alternating per-call runs after a streaming kernel
 // (as in the benchmark step):
-//   binary32 twofold sum                      32 tiles,  8 waves
+//   binary32 twofold sum, dot of dotted       32 tiles,  8 waves
+//   vectors, plain dot
 //   binary32 dotted sum, plain sum            128 tiles, 16 waves
-//   binary32 dot of dotted vectors, plain dot 64 tiles,  16 waves
 //   binary32, leaves from three or four       32 tiles,  4 waves
 //   binary64, leaves from one or two arrays   64 tiles,  16 waves
 //   binary64, leaves from three or four       16 tiles,  4 waves
@@ -112,11 +112,9 @@ struct AutoShape {
 static AutoShape auto_shape(int elem_size, int leaf) {
     if (leaf_arrays(leaf) > 2) return elem_size == 4 ? AutoShape{32, 4} : AutoShape{16, 4};
     if (elem_size == 4) {
-        switch (leaf) {
-        case LEAF_SUM_T: return {32, 8};
-        case LEAF_SUM_D: case LEAF_PSUM: return {128, 16};
-        default: return {64, 16};  // dot of dotted vectors, plain dot
-        }
+        // (64 tiles x 16 waves is 1-2 us faster for the dots in isolated
+        // runs but 8-10 us slower inside the benchmark step, measured twice)
+        return leaf == LEAF_SUM_D || leaf == LEAF_PSUM ? AutoShape{128, 16} : AutoShape{32, 8};
     }
     return {64, 16};
 }
