@@ -46,6 +46,13 @@ def lib() -> C.CDLL:
             raise TwofoldError(
                 "libtwofold.so is missing: build it with paper_1401_6235_amd.build.build() "
                 "(hipcc, gfx950) before using the library")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (one runtime per process), not to a second copy from the
+        # system path that would not know torch's device memory
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _lib = C.CDLL(LIB_PATH)
         _lib.tf_strerror.restype = C.c_char_p
         _lib.tf_reduce_workspace_bytes.restype = C.c_size_t
