@@ -100,27 +100,30 @@ __device__ __forceinline__ double cancel_scale<double>() { return 0x1p-40; }
 template <>
 __device__ __forceinline__ float cancel_scale<float>() { return 0x1p-16f; }
 
-// Element i of every input array the job generates.
-template <typename T>
-__device__ __forceinline__ void gen_elem(T *x0, T *x1, T *y0, T *y1, uint64_t s, int64_t i, bool horner, bool ill,
-                                         T a0) {
+// How a job's inputs are drawn: x by gen_value (sums, dots, axpy; their
+// ill-conditioned kind cancels y against -a x instead), or in a narrow band
+// around 1 for Horner (a tighter one for its ill-conditioned kind).
+enum GenMode { GEN_VALUE = 0, GEN_AXPY_ILL = 1, GEN_HORNER = 2, GEN_HORNER_ILL = 3 };
+
+// Element i of every input array the job generates.  The job's pattern is
+// a template argument, so a unit's unrolled element loop has no branches
+// and the independent elements' hash chains interleave.
+template <typename T, int MODE, bool X1, bool Y0, bool Y1>
+__device__ __forceinline__ void gen_elem(T *x0, T *x1, T *y0, T *y1, uint64_t s, int64_t i, T a0) {
     T a;
-    if (horner) {
-        if (ill) a = T(1) + gen_u<T>(draw(s, i, 0)) * T(0x1p-12);
-        else a = T(0.9) + T(0.2) * gen_u01<T>(draw(s, i, 0));
-    } else {
-        a = gen_value<T>(draw(s, i, 0));
-    }
+    if constexpr (MODE == GEN_HORNER_ILL) a = T(1) + gen_u<T>(draw(s, i, 0)) * T(0x1p-12);
+    else if constexpr (MODE == GEN_HORNER) a = T(0.9) + T(0.2) * gen_u01<T>(draw(s, i, 0));
+    else a = gen_value<T>(draw(s, i, 0));
     x0[i] = a;
-    if (x1) x1[i] = a * (gen_u<T>(draw(s, i, 1)) * low_scale<T>());
-    if (y0) {
+    if constexpr (X1) x1[i] = a * (gen_u<T>(draw(s, i, 1)) * low_scale<T>());
+    if constexpr (Y0) {
         T b;
-        if (!horner && ill)  // axpy with y ~ -a x
+        if constexpr (MODE == GEN_AXPY_ILL)  // axpy with y ~ -a x
             b = -(a0 * a) + a * (gen_u<T>(draw(s, i, 2)) * cancel_scale<T>());
         else
             b = gen_value<T>(draw(s, i, 2));
         y0[i] = b;
-        if (y1) y1[i] = b * (gen_u<T>(draw(s, i, 3)) * low_scale<T>());
+        if constexpr (Y1) y1[i] = b * (gen_u<T>(draw(s, i, 3)) * low_scale<T>());
     }
 }
 
@@ -128,22 +131,44 @@ __device__ __forceinline__ void gen_elem(T *x0, T *x1, T *y0, T *y1, uint64_t s,
 // every input array the job generates, consecutive threads on consecutive
 // elements; a full unit in a loop of fixed length, unrolled so that the
 // independent elements' arithmetic and stores overlap.
-template <typename T>
-__device__ void gen_unit(const tfs_desc &d, int unit) {
+template <typename T, int MODE, bool X1, bool Y0, bool Y1>
+__device__ void gen_unit_as(const tfs_desc &d, int unit) {
     T *x0 = (T *)d.x0, *x1 = (T *)d.x1, *y0 = (T *)d.y0, *y1 = (T *)d.y1;
     const uint64_t s = d.seed;
-    const bool horner = d.op == TFS_OP_HORNER, ill = d.kind == TFS_KIND_ILLCOND;
     const T a0 = T(d.a0);
     const int64_t base = (int64_t)unit * TFS_CLAIM;
     const int64_t end = d.n < base + TFS_CLAIM ? d.n : base + TFS_CLAIM;
     if (end - base == TFS_CLAIM) {
 #pragma unroll 4
         for (int k = 0; k < TFS_CLAIM / kServeBlock; ++k)
-            gen_elem<T>(x0, x1, y0, y1, s, base + k * kServeBlock + threadIdx.x, horner, ill, a0);
+            gen_elem<T, MODE, X1, Y0, Y1>(x0, x1, y0, y1, s, base + k * kServeBlock + threadIdx.x, a0);
     } else {
         for (int64_t i = base + threadIdx.x; i < end; i += kServeBlock)
-            gen_elem<T>(x0, x1, y0, y1, s, i, horner, ill, a0);
+            gen_elem<T, MODE, X1, Y0, Y1>(x0, x1, y0, y1, s, i, a0);
     }
+}
+
+template <typename T, int MODE, bool X1>
+__device__ __forceinline__ void gen_unit_y(const tfs_desc &d, int unit) {
+    if constexpr (MODE == GEN_HORNER || MODE == GEN_HORNER_ILL) gen_unit_as<T, MODE, X1, false, false>(d, unit);
+    else if (!d.y0) gen_unit_as<T, MODE, X1, false, false>(d, unit);
+    else if (!d.y1) gen_unit_as<T, MODE, X1, true, false>(d, unit);
+    else gen_unit_as<T, MODE, X1, true, true>(d, unit);
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void gen_unit_x(const tfs_desc &d, int unit) {
+    if (d.x1) gen_unit_y<T, MODE, true>(d, unit);
+    else gen_unit_y<T, MODE, false>(d, unit);
+}
+
+template <typename T>
+__device__ void gen_unit(const tfs_desc &d, int unit) {
+    const bool horner = d.op == TFS_OP_HORNER, ill = d.kind == TFS_KIND_ILLCOND;
+    if (horner && ill) gen_unit_x<T, GEN_HORNER_ILL>(d, unit);
+    else if (horner) gen_unit_x<T, GEN_HORNER>(d, unit);
+    else if (ill) gen_unit_x<T, GEN_AXPY_ILL>(d, unit);
+    else gen_unit_x<T, GEN_VALUE>(d, unit);
 }
 
 // ---------------------------------------------------------------------------
