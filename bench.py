@@ -68,16 +68,43 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without its comments (string and character literals kept
+    as they are), each comment replaced by one space."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources the profiled kernels are built from: every HIP
+    """Hash of the code the profiled kernels are built from: every HIP
     source and header of the library except the serving loop's
     (tf_serve*), which none of the step, chain or application kernels
-    includes."""
+    includes, with comments left out (a comment edit does not change the
+    kernels, so it keeps the profiles valid)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1401_6235_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")) and not name.startswith("tf_serve"):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+            h.update(strip_comments(open(os.path.join(csrc, name)).read()).encode())
     return h.hexdigest()[:16]
 
 

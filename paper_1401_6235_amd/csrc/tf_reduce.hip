@@ -6,16 +6,16 @@
 // tree and the result is bitwise reproducible.
 //
 // Mapping onto gfx950:
-//   * one wave reduces one tile (tf_tree.hpp);
-//   * one block of 4 waves reduces an aligned group of `per_block` tiles
-//     (a subtree): each wave folds its consecutive tiles with a binary
-//     counter (subtrees of 1, 2, 4, ... tiles merged as they complete), and
-//     thread 0 joins the (at most 4) wave results;
+//   * one wave reduces one tile, or a group of two (binary64) or four
+//     (binary32) adjacent tiles at a time (tf_tree.hpp);
+//   * one block of 4, 8 or 16 waves reduces an aligned group of
+//     `per_block` tiles (a subtree): each wave takes per_block / waves
+//     consecutive tiles, lane t keeps the value of the wave's tile t and a
+//     butterfly finishes the wave's aligned group; the waves' results meet
+//     in LDS and one more butterfly joins them, so every tree level above
+//     the leaves stays in registers;
 //   * the per-block partials are joined by the same pairing in one more
-//     pass (a second pass only when there are more than 16384 of them).
-//   * within a block, lane t of a wave keeps the wave's t-th subtree value
-//     and a butterfly finishes the wave's aligned group: every tree level
-//     stays in registers.
+//     pass, one block of 16 waves (middle passes only past 65536 of them).
 #include "tf_tree.hpp"
 
 

@@ -97,3 +97,15 @@ def test_summarizer_on_a_miniature_profile(tmp_path):
     assert row["add_f64"][1:4] == ["1", "2.00", str(big[ADD64])]
     ratios = [l.split()[-1] for l in open(out / "hot_path_step_n2e28_counters.txt") if l.startswith(("add_", "sum_"))]
     assert ratios == ["1.0000", "1.0000"]
+
+
+def test_source_hash_ignores_comments_only():
+    src = ('int a = 1; // note\nconst char *s = "x // kept /* kept */"; /* block\n comment */ char q = \'/\';\n'
+           "char e = '\\''; // end")
+    out = bench.strip_comments(src)
+    assert "note" not in out and "block" not in out and "end" not in out
+    assert '"x // kept /* kept */"' in out and "'/'" in out and "'\\''" in out
+    assert bench.strip_comments("a = b / c; // x") == "a = b / c;  "
+    # a comment edit keeps the hash, a code edit changes it
+    assert bench.strip_comments("x = 1; // one") == bench.strip_comments("x = 1; // two")
+    assert bench.strip_comments("x = 1;") != bench.strip_comments("x = 2;")
