@@ -109,3 +109,12 @@ def test_source_hash_ignores_comments_only():
     # a comment edit keeps the hash, a code edit changes it
     assert bench.strip_comments("x = 1; // one") == bench.strip_comments("x = 1; // two")
     assert bench.strip_comments("x = 1;") != bench.strip_comments("x = 2;")
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
