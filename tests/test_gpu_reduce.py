@@ -4,7 +4,8 @@ Covers every leaf kind (dotted and twofold sums; dotted, twofold and mixed
 dots; plain sum and dot), sizes from 0 to the full n = 2^26 instances of
 the ill-conditioned dot generator (condition numbers 1e4 .. 1e32 in
 binary64, 1e4 .. 1e16 in binary32), ragged tails, misaligned views, and
-every reduction block geometry (the tree must not depend on it).
+every reduction block geometry (the tree must not depend on it), and sizes
+around the tuned shapes' block boundaries.
 """
 import numpy as np
 import pytest
@@ -65,6 +66,28 @@ def test_all_leaf_kinds(n, dtype):
     got, want = gpu_all(*case), oracle_all(*case)
     for k in want:
         assert_bits(got[k], want[k], "%s n=%d" % (k, n))
+
+
+def _boundary_sizes():
+    """Sizes around the tuned first-pass shapes' block boundaries: tile
+    counts at small multiples of 32, 64 and 128 tiles and one tile or one
+    leaf either side (every third of them, to bound the oracle's time)."""
+    sizes = set()
+    for pb in (32, 64, 128):
+        for m in (1, 2, 3, 7, 63, 64, 65):
+            for d in (-257, -1, 0, 1, 255, 256, 257):
+                sizes.add(pb * m * 256 + d)
+    return sorted(sizes)[::3]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tuned_shape_block_boundaries(dtype):
+    for n in _boundary_sizes():
+        step("shape boundary n=%d %s" % (n, np.dtype(dtype)))
+        case = random_case(n, dtype, n % 9973)
+        got, want = gpu_all(*case), oracle_all(*case)
+        for k in want:
+            assert_bits(got[k], want[k], "%s n=%d" % (k, n))
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
