@@ -250,6 +250,64 @@ def test_full_size_sampled(dtype):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_full_size_binary_ops_sampled(dtype):
+    """The benchmark step's twofold add, sub, mul, div and sqrt at n = 2^28
+    in its launch configuration, both operands twofold.  Inputs are seeded
+    on the device (torch's generator: sign-uniform high parts of magnitude
+    in [0.5, 1.5) times a power of two in 2^-20 .. 2^20, low parts about
+    one unit in the last place of them; positive for the square root);
+    100k sampled outputs, the first and last ones among them, are checked
+    one by one against the oracle."""
+    torch = torch_cuda()
+    n = 1 << 28
+    dt = torch.float32 if dtype == np.float32 else torch.float64
+    ulp = 2.0 ** -24 if dtype == np.float32 else 2.0 ** -53
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2028)
+
+    def hi(positive=False):
+        v = (torch.rand(n, generator=gen, device="cuda", dtype=dt) + 0.5)
+        v = v * torch.exp2(torch.randint(-20, 21, (n,), generator=gen, device="cuda").to(dt))
+        if positive:
+            return v
+        sign = torch.randint(0, 2, (n,), generator=gen, device="cuda", dtype=torch.int8)
+        return torch.where(sign == 1, -v, v)
+
+    def lo(h):
+        return h * ((torch.rand(n, generator=gen, device="cuda", dtype=dt) * 2 - 1) * ulp)
+
+    g = np.random.default_rng(29)
+    idx = np.unique(np.concatenate([g.integers(0, n, 100000), [0, 1, n - 2, n - 1]]))
+    ii = torch.from_numpy(idx).cuda()
+    name = np.dtype(dtype).name
+    step("full-size binary ops %s n=2^28 (generate)" % name)
+    x0 = hi()
+    x1 = lo(x0)
+    y0 = hi()
+    y1 = lo(y0)
+    z0, z1 = torch.empty_like(x0), torch.empty_like(x0)
+    hx = [t.index_select(0, ii).cpu().numpy() for t in (x0, x1, y0, y1)]
+    for op in ("add", "sub", "mul", "div"):
+        step("full-size %s %s n=2^28" % (op, name))
+        getattr(tf, "tf_" + op)(x0, x1, y0, y1, z0, z1)
+        torch.cuda.synchronize()
+        want = getattr(oracle, op)(*hx)
+        assert_bits(to_np(z0.index_select(0, ii)), want[0], "%s z0" % op)
+        assert_bits(to_np(z1.index_select(0, ii)), want[1], "%s z1" % op)
+    del y0, y1
+    step("full-size sqrt %s n=2^28" % name)
+    s0 = hi(positive=True)
+    s1 = lo(s0)
+    tf.tf_sqrt(s0, s1, z0, z1)
+    torch.cuda.synchronize()
+    want = oracle.sqrt(s0.index_select(0, ii).cpu().numpy(), s1.index_select(0, ii).cpu().numpy())
+    assert_bits(to_np(z0.index_select(0, ii)), want[0], "sqrt z0")
+    assert_bits(to_np(z1.index_select(0, ii)), want[1], "sqrt z1")
+    del x0, x1, s0, s1, z0, z1
+    torch.cuda.empty_cache()
+
+
 def test_repeat_and_grid_cap_are_bitwise_stable():
     torch = torch_cuda()
     c = W.elementwise("div", 1 << 20, seed=3)
